@@ -1,0 +1,169 @@
+"""Truncated local trace Tr_R(c) by dense eigendecomposition (FP64).
+
+Definition followed (trace factor of Eq.(2), Sec. II; truncation of type (i),
+Sec. II; evaluation steps 3-8 of Sec. III):
+
+    Tr_R(c) = sum_{i in R} <E_i| e^{-(beta - tau_n) H} O_n e^{-(tau_n - tau_{n-1}) H}
+                                ... O_1 e^{-tau_1 H} |E_i>
+
+with O_k = c^dag_{f_k} if dagger_k else c_{f_k}, 0 <= tau_1 < ... < tau_n < beta.
+The value is the literal operator product in time order (latest operator
+leftmost); no time-ordering permutation sign is attached.
+
+Each imaginary-time evolution inside block b is written out as the matrix
+function V_b diag(exp(-dtau (E_b - E0))) V_b^T from the block's eigen-
+decomposition.  Because |E_i> is an eigenstate, the two edge intervals reduce
+to the scalar exp(-(beta - tau_n + tau_1) (E_i - E0)) (step 3).  Energies are
+shifted by the ground energy E0 and the vector is renormalised after every
+step with its log-norm kept aside; these are exact rescalings that keep the
+float64 numbers in range, and -beta*E0 is added back at the end.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+import numpy as np
+
+from .fock import FockOperators, block_key
+from .hamiltonian import BlockSpectrum, Retained
+
+
+@dataclass
+class TraceResult:
+    sign: np.ndarray          # int8 [n_configs]: -1, 0, +1
+    log_abs: np.ndarray       # float64: log|Tr_R|, -inf where sign = 0
+    contrib_sign: np.ndarray  # int8 [n_configs, n_retained]
+    contrib_log: np.ndarray   # float64 [n_configs, n_retained]: log|t_i| incl. -beta*E0
+    feasible: np.ndarray      # bool [n_configs, n_retained]: sector path stays physical
+
+    def kappa(self):
+        """Conditioning sum_i |t_i| / |sum_i t_i| per config (inf for zero traces)."""
+        out = np.full(len(self.sign), np.inf)
+        for c in range(len(self.sign)):
+            if self.sign[c] == 0:
+                continue
+            lg = self.contrib_log[c]
+            m = np.max(lg)
+            s_abs = np.sum(np.exp(lg - m))
+            out[c] = s_abs * np.exp(m - self.log_abs[c])
+        return out
+
+
+class TraceOracle:
+    """Holds a block spectrum, a retained set and cached operator blocks."""
+
+    def __init__(self, spec: BlockSpectrum, retained: Retained, ops: FockOperators | None = None):
+        self.spec = spec
+        self.R = retained
+        self.n = spec.n_orb
+        self.ops = ops or FockOperators(self.n)
+        self._opblk = {}
+
+    # -- sector bookkeeping -------------------------------------------------
+    def _nud(self, b):
+        return b % (self.n + 1), b // (self.n + 1)
+
+    def target_block(self, b: int, f: int, dagger: int) -> int:
+        """Block reached by O from block b, or -1 if it leaves the physical range."""
+        nu, nd = self._nud(b)
+        d = 1 if dagger else -1
+        if f < self.n:
+            nu += d
+        else:
+            nd += d
+        if not (0 <= nu <= self.n and 0 <= nd <= self.n):
+            return -1
+        return block_key(self.n, nu, nd)
+
+    def op_block(self, f: int, dagger: int, b: int):
+        """Dense matrix of O restricted to block b -> target block."""
+        key = (f, dagger, b)
+        if key not in self._opblk:
+            bt = self.target_block(b, f, dagger)
+            M = self.ops.op(f, dagger)
+            src, dst = self.spec.states[b], self.spec.states[bt]
+            self._opblk[key] = (bt, M[dst][:, src].toarray())
+        return self._opblk[key]
+
+    def propagate(self, b: int, v: np.ndarray, dtau: float) -> np.ndarray:
+        """exp(-dtau (H_b - E0)) v by the eigendecomposition of block b."""
+        Vb, Eb = self.spec.V[b], self.spec.E[b]
+        return Vb @ (np.exp(-dtau * (Eb - self.spec.E0)) * (Vb.T @ v))
+
+    # -- one term of the outer sum ------------------------------------------
+    def path(self, tau, flavor, dagger, beta: float, r: int):
+        """(feasible, sign, log|t_r|) for retained state r (log includes -beta*E0)."""
+        b0 = int(self.R.block[r])
+        Ei = float(self.R.energy[r])
+        E0 = self.spec.E0
+        nops = len(tau)
+        # sector path first (block-level structural zeros, no arithmetic)
+        b = b0
+        for k in range(nops):
+            b = self.target_block(b, int(flavor[k]), int(dagger[k]))
+            if b < 0:
+                return False, 0, -np.inf
+        if b != b0:
+            return False, 0, -np.inf
+        ei = self.spec.V[b0][:, int(self.R.index[r])]
+        if nops == 0:
+            return True, 1, -beta * (Ei - E0) - beta * E0
+        ell = -(beta - tau[-1] + tau[0]) * (Ei - E0)
+        v = ei.copy()
+        b = b0
+        for k in range(nops):
+            if k > 0:
+                v = self.propagate(b, v, float(tau[k] - tau[k - 1]))
+                s = np.linalg.norm(v)
+                if s == 0.0:
+                    return True, 0, -np.inf
+                ell += np.log(s)
+                v = v / s
+            b, M = self.op_block(int(flavor[k]), int(dagger[k]), b)
+            v = M @ v
+            s = np.linalg.norm(v)
+            if s == 0.0:
+                return True, 0, -np.inf
+            ell += np.log(s)
+            v = v / s
+        ov = float(ei @ v)
+        if ov == 0.0:
+            return True, 0, -np.inf
+        return True, (1 if ov > 0 else -1), ell + np.log(abs(ov)) - beta * E0
+
+    # -- the batch -----------------------------------------------------------
+    def trace_batch(self, batch, configs=None) -> TraceResult:
+        idx = range(batch.n_configs) if configs is None else list(configs)
+        idx = list(idx)
+        nR = len(self.R.block)
+        sg = np.zeros(len(idx), np.int8)
+        la = np.full(len(idx), -np.inf)
+        csg = np.zeros((len(idx), nR), np.int8)
+        clg = np.full((len(idx), nR), -np.inf)
+        feas = np.zeros((len(idx), nR), bool)
+        for j, c in enumerate(idx):
+            tau, fl, dg = batch.config(c)
+            for r in range(nR):
+                feas[j, r], csg[j, r], clg[j, r] = self.path(tau, fl, dg, batch.beta, r)
+            sg[j], la[j] = signed_logsum(csg[j], clg[j])
+        return TraceResult(sg, la, csg, clg, feas)
+
+
+def signed_logsum(signs, logs):
+    """(sign, log|sum_i sign_i exp(log_i)|) in a fixed order; sign 0 for an exact zero."""
+    nz = signs != 0
+    if not np.any(nz):
+        return 0, -np.inf
+    m = np.max(logs[nz])
+    s = float(np.sum(signs[nz] * np.exp(logs[nz] - m)))
+    if s == 0.0:
+        return 0, -np.inf
+    return (1 if s > 0 else -1), m + np.log(abs(s))
+
+
+def build(params, window: float, ops: FockOperators | None = None, hc_literal: bool = False):
+    """Convenience: spectrum + retained set + oracle for a parameter set."""
+    from .hamiltonian import block_spectrum, retained_set
+    ops = ops or FockOperators(params.n_orb)
+    spec = block_spectrum(params, hc_literal=hc_literal, ops=ops)
+    R = retained_set(spec, window)
+    return TraceOracle(spec, R, ops)

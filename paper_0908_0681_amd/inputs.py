@@ -1,0 +1,204 @@
+"""Seeded synthetic inputs shared by the oracle tests and the HIP path.
+
+This module holds only input recipes: model parameters of the Kanamori
+impurity of Eq.(4) (Sec. IV.A), and random hybridization-event configurations
+(the configurations c~ of Eq.(2), Sec. II).  It contains none of the trace
+arithmetic, so that both sides of a parity test read identical bytes without
+sharing any of the method's code.
+
+Conventions fixed here (they are input conventions, not arithmetic):
+
+* flavor index f = a + n_orb * sigma, sigma = 0 for spin up, 1 for spin down;
+* a configuration is a time-ordered list of operators (tau, flavor, dagger)
+  with 0 <= tau_1 < ... < tau_n < beta; dagger = 1 is a creator;
+* a batch of configurations is CSR: ops of config c are
+  [offsets[c], offsets[c+1]).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+import numpy as np
+
+
+# --------------------------------------------------------------------------
+# model parameters
+# --------------------------------------------------------------------------
+
+def mu_half(n_orb: int, U: float, J: float) -> float:
+    """Half-filling chemical potential of the rotationally invariant model
+    (Sec. IV.B): (n - 1/2) U - (n - 1) (5/2) J."""
+    return (n_orb - 0.5) * U - (n_orb - 1) * 2.5 * J
+
+
+@dataclass
+class ModelParams:
+    """Parameters of the Kanamori H_loc of Eq.(4).
+
+    eps[a] is the spin-independent one-body energy -(mu + Delta_a);
+    U intra-orbital, Up inter-orbital opposite spin, Up - J same spin,
+    J_sf / J_ph the spin-flip / pair-hopping amplitudes (both J in Eq.(4)).
+    """
+    n_orb: int
+    eps: np.ndarray
+    U: float
+    Up: float
+    J: float
+    J_sf: float
+    J_ph: float
+
+    @property
+    def n_flavors(self) -> int:
+        return 2 * self.n_orb
+
+
+def kanamori(n_orb: int, U: float, J: float, mu: float,
+             delta=None, density_density: bool = False) -> ModelParams:
+    """Rotationally invariant Kanamori parameters, U' = U - 2J (Sec. IV.A)."""
+    delta = np.zeros(n_orb) if delta is None else np.asarray(delta, dtype=np.float64)
+    eps = -(mu + delta)
+    jx = 0.0 if density_density else J
+    return ModelParams(n_orb=n_orb, eps=np.ascontiguousarray(eps, dtype=np.float64),
+                       U=float(U), Up=float(U - 2.0 * J), J=float(J),
+                       J_sf=float(jx), J_ph=float(jx))
+
+
+def crystal_field(n_orb: int, amp: float, seed: int) -> np.ndarray:
+    """Crystal-field shifts Delta_a ~ U(-amp, amp), spin independent."""
+    rng = np.random.default_rng(seed)
+    return rng.uniform(-amp, amp, size=n_orb)
+
+
+# --------------------------------------------------------------------------
+# configurations
+# --------------------------------------------------------------------------
+
+@dataclass
+class ConfigBatch:
+    offsets: np.ndarray      # int64 [n_configs + 1]
+    tau: np.ndarray          # float64 [n_ops]
+    flavor: np.ndarray       # int16 [n_ops]
+    dagger: np.ndarray       # int8 [n_ops]
+    beta: float
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n_configs(self) -> int:
+        return len(self.offsets) - 1
+
+    def config(self, c: int):
+        s, e = int(self.offsets[c]), int(self.offsets[c + 1])
+        return self.tau[s:e], self.flavor[s:e], self.dagger[s:e]
+
+    def subset(self, idx) -> "ConfigBatch":
+        return from_lists([self.config(int(c)) for c in idx], self.beta)
+
+
+def from_lists(cfgs, beta: float) -> ConfigBatch:
+    """Build a batch from a list of (tau, flavor, dagger) triples."""
+    offs = [0]
+    taus, fls, dgs = [], [], []
+    for tau, fl, dg in cfgs:
+        taus.append(np.asarray(tau, dtype=np.float64))
+        fls.append(np.asarray(fl, dtype=np.int16))
+        dgs.append(np.asarray(dg, dtype=np.int8))
+        offs.append(offs[-1] + len(taus[-1]))
+    cat = lambda xs, dt: (np.concatenate(xs).astype(dt) if xs else np.zeros(0, dt))
+    return ConfigBatch(offsets=np.asarray(offs, dtype=np.int64),
+                       tau=np.ascontiguousarray(cat(taus, np.float64)),
+                       flavor=np.ascontiguousarray(cat(fls, np.int16)),
+                       dagger=np.ascontiguousarray(cat(dgs, np.int8)),
+                       beta=float(beta))
+
+
+def random_config(rng: np.random.Generator, n_orb: int, beta: float, lam: float,
+                  start: str = "reference"):
+    """One configuration: per-flavor order k_f ~ Poisson(lam), 2 k_f operator
+    times uniform in [0, beta), per-flavor alternation of c / c^dag in time.
+
+    start = "reference": a reference Fock state with every orbital singly
+    occupied and a random spin per orbital is drawn; a flavor occupied in it
+    starts with an annihilator, otherwise with a creator (this keeps the
+    sector path inside the physical range, so the truncated trace is rarely a
+    structural zero).  start = "random": the first type of every flavor is a
+    fair coin (most truncated traces are then structural zeros).
+    """
+    F = 2 * n_orb
+    spins = rng.integers(0, 2, size=n_orb)
+    occ = np.zeros(F, dtype=bool)
+    for a in range(n_orb):
+        occ[a + n_orb * spins[a]] = True
+    k = rng.poisson(lam, size=F)
+    taus, fls = [], []
+    for f in range(F):
+        taus.append(rng.uniform(0.0, beta, size=2 * k[f]))
+        fls.append(np.full(2 * k[f], f, dtype=np.int16))
+    tau = np.concatenate(taus) if taus else np.zeros(0)
+    fl = np.concatenate(fls) if fls else np.zeros(0, np.int16)
+    order = np.argsort(tau, kind="stable")
+    tau, fl = tau[order], fl[order]
+    if len(tau) > 1 and np.any(np.diff(tau) <= 0.0):   # measure-zero tie: redraw
+        return random_config(rng, n_orb, beta, lam, start)
+    dg = np.zeros(len(tau), dtype=np.int8)
+    for f in range(F):
+        pos = np.nonzero(fl == f)[0]
+        if start == "reference":
+            first_creator = not occ[f]
+        else:
+            first_creator = bool(rng.integers(0, 2))
+        # alternate in time order
+        dg[pos] = np.where((np.arange(len(pos)) % 2 == 0) == first_creator, 1, 0)
+    return tau, fl, dg
+
+
+def random_batch(seed: int, n_orb: int, n_configs: int, beta: float, lam: float,
+                 start: str = "reference") -> ConfigBatch:
+    rng = np.random.default_rng(seed)
+    cfgs = [random_config(rng, n_orb, beta, lam, start) for _ in range(n_configs)]
+    b = from_lists(cfgs, beta)
+    b.meta = dict(seed=seed, n_orb=n_orb, lam=lam, start=start)
+    return b
+
+
+# --------------------------------------------------------------------------
+# the workloads of the benchmark table
+# --------------------------------------------------------------------------
+
+MODEL_SEED = 1
+
+
+@dataclass
+class Workload:
+    name: str
+    params: ModelParams
+    beta: float
+    n_configs: int
+    lam: float
+    config_seed: int
+    precision: str            # "fp64" | "mixed"
+    retain_window: float      # < 0: every state (full trace)
+    krylov_max: int = 20
+    krylov_tol: float = 1e-12
+
+    def batch(self, n_configs: int | None = None, start: str = "reference") -> ConfigBatch:
+        n = self.n_configs if n_configs is None else n_configs
+        return random_batch(self.config_seed, self.params.n_orb, n, self.beta, self.lam, start)
+
+
+def workload(k: int) -> Workload:
+    """Workload k of the benchmark table (k = 0, 1, 2)."""
+    if k == 0:
+        # 2 orbitals, eps = -mu, mu = (3U - 5J)/2, U = 4, J = 1, beta = 10
+        p = kanamori(2, U=4.0, J=1.0, mu=(3 * 4.0 - 5 * 1.0) / 2)
+        return Workload("kanamori-2orb-b10", p, 10.0, 64, 2.0, 1000, "fp64", -1.0)
+    if k == 1:
+        U, J = 4.0, 1.0
+        p = kanamori(5, U=U, J=J, mu=mu_half(5, U, J),
+                     delta=crystal_field(5, 0.1, MODEL_SEED))
+        return Workload("kanamori-5orb-b50", p, 50.0, 4096, 5.0, 1001, "fp64", 1e-5)
+    if k == 2:
+        U, J = 6.0, 0.7
+        p = kanamori(7, U=U, J=J, mu=mu_half(7, U, J),
+                     delta=crystal_field(7, 0.05, MODEL_SEED))
+        return Workload("kanamori-7orb-b40", p, 40.0, 1024, 6.0, 1002, "mixed", 1e-5,
+                        krylov_max=20, krylov_tol=1e-7)
+    raise ValueError(k)
