@@ -1,0 +1,213 @@
+/*
+ * hyb.h -- C ABI of the MI355X (gfx950) Krylov hybridization-expansion trace library.
+ *
+ * Method: Laeuchli & Werner, "Krylov-implementation of the hybridization
+ * expansion impurity solver and application to 5-orbital models"
+ * (arXiv:0908.0681).  The library evaluates the truncated local trace of the
+ * Monte Carlo weight, Eq.(2) (Sec. II),
+ *
+ *   Tr_R(c) = sum_{i in R} <E_i| e^{-(beta-tau_n) H} O_n e^{-(tau_n-tau_{n-1}) H} ... O_1 e^{-tau_1 H} |E_i>,
+ *
+ * in the occupation-number basis with sparse H_loc (Kanamori form, Eq.(4),
+ * Sec. IV.A) and Krylov (Lanczos) time evolution (Sec. III, steps 3-8), summed
+ * over the retained low-energy states R (truncation of type (i), Sec. II).
+ *
+ * General conventions
+ *  - Every function returns an int status: HYB_OK (0) or a negative HYB_E_*
+ *    code.  No C++ exception and no abort crosses this boundary.
+ *    hyb_last_error() returns a thread-local human-readable message for the
+ *    last failing call on the calling thread.
+ *  - The caller owns every input and output buffer.  The library owns the
+ *    opaque handles; each *_create / hyb_build_hloc has a matching destroy.
+ *  - "stream" arguments are a hipStream_t passed as void* (NULL = the null
+ *    stream).  Device work is enqueued on that stream.  Calls whose outputs are
+ *    host memory synchronise that stream before returning.
+ *  - Flavor f = a + n_orb * sigma (orbital a, sigma = 0 up / 1 down).  Bit f
+ *    of a basis-state integer is the occupation of flavor f.  Fermion signs
+ *    follow the Jordan-Wigner string in flavor order:
+ *      c_f |s> = (-1)^{popcount(s & ((1<<f)-1))} |s ^ (1<<f)>  if bit f of s is set.
+ *  - Blocks are the (n_up, n_dn) quantum-number sectors (Sec. II, quantum
+ *    number ordering; Sec. IV.C orders them with n_up fastest):
+ *      block = n_dn * (n_orb + 1) + n_up,
+ *    and states inside a block are ordered by ascending state integer.
+ */
+#ifndef HYB_H
+#define HYB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------- */
+#define HYB_OK            0
+#define HYB_E_ARG        -1  /* invalid argument (NULL pointer, size or range) */
+#define HYB_E_UNSORTED   -2  /* operator times not strictly increasing or outside [0, beta) */
+#define HYB_E_FLAVOR     -3  /* flavor index outside [0, 2*n_orb) or dagger not 0/1 */
+#define HYB_E_NOCONV     -4  /* Krylov propagation exceeded the substep limit */
+#define HYB_E_NONFINITE  -5  /* NaN / Inf met in an input or intermediate */
+#define HYB_E_HIP        -6  /* a HIP runtime call failed */
+#define HYB_E_OOM        -7  /* host or device allocation failed */
+#define HYB_E_STATE      -8  /* handle used in a state that does not allow the call */
+
+/* ---- model --------------------------------------------------------------- */
+#define HYB_CSR          0   /* H_loc blocks stored as CSR */
+#define HYB_FP64         0   /* Krylov vectors, SpMV and recurrences in float64 */
+#define HYB_MIXED        1   /* float32 Krylov vectors and off-diagonal SpMV with float32
+                                accumulation; float64 diagonal, Lanczos alpha/beta,
+                                re-orthogonalisation coefficients, tridiagonal exponential
+                                and running log-norm */
+
+typedef struct {
+  int32_t n_orb;          /* orbitals, 1..7 (F = 2*n_orb flavors <= 14) */
+  const double* eps;      /* host [n_orb]: one-body energy of orbital a, -(mu + Delta_a) (Eq.(4)) */
+  double U;               /* intra-orbital repulsion (Eq.(4)) */
+  double Up;              /* inter-orbital opposite-spin repulsion U'; same spin gets Up - J */
+  double J;               /* Hund coupling in the density-density part (Up - J) */
+  double J_sf;            /* spin-flip amplitude (J in Eq.(4); 0 gives a density-density model) */
+  double J_ph;            /* pair-hopping amplitude (J in Eq.(4)) */
+  int32_t storage;        /* HYB_CSR */
+  int32_t precision;      /* HYB_FP64 or HYB_MIXED */
+  double retain_window;   /* retained set R = {E_i - E0 <= retain_window}; < 0: all states
+                             (full trace).  Sec. III step 2, Sec. IV.C (energy window) */
+  int32_t krylov_max;     /* Lanczos depth cap per (sub)interval, 2..20 (the tuned kernels
+                             support 12, 16 and 20; the cap is rounded up to one of them
+                             for register sizing but never exceeded) */
+  double krylov_tol;      /* a-posteriori relative tolerance per (sub)interval:
+                             beta_m |[exp(-dtau T_m)]_{m,1}| / ||exp(-dtau T_m) e_1|| <= tol.
+                             Sec. III step 5 leaves the criterion open; this is the
+                             Saad (1992) estimate.  Typical 1e-13 (FP64), 1e-7 (mixed). */
+} hyb_model_params;
+
+typedef struct hyb_model hyb_model;
+
+typedef struct {
+  int32_t n_orb, n_flavors, n_blocks, max_dim, n_retained, precision;
+  int64_t n_states, nnz_offdiag;
+  double E0;              /* lowest eigenvalue of H_loc */
+} hyb_model_info_t;
+
+/* Builds the bit-encoded basis, the (n_up, n_dn) blocks, H_loc per block (Eq.(4)
+ * with spin-flip and pair-hopping summed once per ordered orbital pair a != b),
+ * the spectrum of every block by dense FP64 Householder tridiagonalisation and
+ * implicit QL (Sec. III step 1, full diagonalisation), E0 and the retained set
+ * (step 2).  Host memory only; no GPU is touched.  *out receives a new handle. */
+int hyb_model_create(const hyb_model_params* p, hyb_model** out);
+
+/* Copies the model (basis tables, CSR blocks, retained vectors) to the current
+ * HIP device on `stream`.  Must precede any device call on the model. */
+int hyb_model_upload(hyb_model* m, void* stream);
+
+/* hyb_model_create + hyb_model_upload. */
+int hyb_build_hloc(const hyb_model_params* p, void* stream, hyb_model** out);
+
+void hyb_model_destroy(hyb_model* m);
+
+int hyb_model_info(const hyb_model* m, hyb_model_info_t* out);
+
+/* Per-block data (host). dim / nnz_offdiag / e_min may be NULL. */
+int hyb_block_info(const hyb_model* m, int32_t block, int32_t* dim, int32_t* nnz_offdiag, double* e_min);
+
+/* Block spectrum (host): e[0..dim) ascending eigenvalues of block `block`. */
+int hyb_block_eigenvalues(const hyb_model* m, int32_t block, double* e);
+
+/* Basis parity hooks (host): state integer <-> (block, index in block). */
+int hyb_basis_state(const hyb_model* m, int32_t block, int32_t idx, uint32_t* bits);
+int hyb_basis_index(const hyb_model* m, uint32_t bits, int32_t* block, int32_t* idx);
+
+/* Dense copy of H_loc restricted to a block (host), row-major dim x dim. */
+int hyb_block_dense(const hyb_model* m, int32_t block, double* h);
+
+/* Retained set (host). block[n_retained], energy[n_retained]; vec (optional) receives
+ * the eigenvectors concatenated in retained order, each of its block's dim. */
+int hyb_retained(const hyb_model* m, int32_t* block, double* energy, double* vec);
+
+/* Host reference application of c_f (dagger = 0) or c_f^dag (dagger = 1) to a
+ * vector x of block block_in (Sec. III, operator application).  *block_out gets
+ * the target block or -1 if the operator leaves the physical range (then y is
+ * untouched).  y has the target block's dimension. */
+int hyb_apply_op(const hyb_model* m, int32_t flavor, int32_t dagger, int32_t block_in,
+                 const double* x, int32_t* block_out, double* y);
+
+/* ---- device parity hooks --------------------------------------------------- */
+
+/* Device operator application (the signed gather of the trace kernels) to n_vec
+ * vectors of block block_in.  x: device [n_vec][dim_in], y: device [n_vec][dim_out].
+ * Bit-exact: only sign flips and moves. */
+int hyb_apply_op_device(hyb_model* m, int32_t flavor, int32_t dagger, int32_t block_in,
+                        int32_t n_vec, const double* x, double* y, int32_t* block_out, void* stream);
+
+/* Device Krylov propagation (Sec. III step 5) of n_vec vectors of one block over
+ * dtau[v] each:  y_v = exp(-dtau_v (H_b - E0)) x_v / s_v with log(s_v) in log_scale[v]
+ * and the normalised result in y.  Lanczos steps used in steps[v] (may be NULL).
+ * All pointers are device; x and y are [n_vec][dim] in the model's precision
+ * (float64 for HYB_FP64, float32 for HYB_MIXED). */
+int hyb_propagate_device(hyb_model* m, int32_t block, int32_t n_vec, const void* x,
+                         const double* dtau, void* y, double* log_scale, int32_t* steps,
+                         void* stream);
+
+/* ---- the hot path: batched traces ----------------------------------------- */
+
+typedef struct {
+  int32_t n_configs;
+  const int64_t* offsets; /* [n_configs + 1]; ops of config c are [offsets[c], offsets[c+1]) */
+  const double* tau;      /* [n_ops] strictly increasing in [0, beta) inside a config */
+  const int16_t* flavor;  /* [n_ops] */
+  const int8_t* dagger;   /* [n_ops] 1 = creator c^dag, 0 = annihilator c */
+  int32_t on_device;      /* 1: the five arrays are device pointers, 0: host */
+} hyb_config_batch;
+
+typedef struct {
+  double* log_abs;        /* [n_configs] log|Tr_R| (includes -beta*E0); -inf when sign = 0 */
+  int8_t* sign;           /* [n_configs] -1, 0, +1.  A zero trace is not an error. */
+  int32_t* krylov_steps;  /* optional [n_configs]: Lanczos steps summed over the config's paths */
+  int32_t* substeps;      /* optional [n_configs]: extra substeps forced by the depth cap */
+  int32_t* feasible_paths;/* optional [n_configs]: retained states whose sector path stays physical */
+  int32_t on_device;      /* 1: outputs are device pointers (no host sync), 0: host */
+} hyb_trace_out;
+
+/* Evaluates Tr_R for every configuration of the batch (Eq.(2) trace factor;
+ * Sec. III steps 3-8): one persistent launch walks all feasible (config,
+ * retained state) paths, alternating operator application and Krylov
+ * propagation with a running log-norm, then a signed log-sum over R per config.
+ * The returned value is the literal operator product in time order (latest
+ * operator leftmost) without a time-ordering permutation sign.
+ * Errors: HYB_E_UNSORTED / HYB_E_FLAVOR for bad configurations (checked on the
+ * device; the call synchronises `stream` to read the check), HYB_E_NOCONV if a
+ * propagation needs more than 64 substeps, HYB_E_NONFINITE for NaN/Inf. */
+int hyb_trace_batch(hyb_model* m, const hyb_config_batch* cfg, double beta,
+                    hyb_trace_out* out, void* stream);
+
+/* Kernel tuning: which trace-kernel variant hyb_trace_batch launches.
+ * variant < 0 restores the automatic choice. Returns HYB_E_ARG for an unknown id. */
+int hyb_set_trace_variant(hyb_model* m, int32_t variant);
+int hyb_get_trace_variant(const hyb_model* m, int32_t* variant);
+/* Number of trace-kernel variants compiled in and a short name of each. */
+int hyb_trace_variant_count(int32_t* n);
+int hyb_trace_variant_name(int32_t variant, char* buf, size_t len);
+
+/* Device time of the last hyb_trace_batch, split by kernel (HIP events on the
+ * call's stream): ms[0] = scan, ms[1] = trace kernel, ms[2] = reduce.  Requires
+ * hyb_set_timing(m, 1) before the call. */
+int hyb_set_timing(hyb_model* m, int32_t on);
+int hyb_last_timing(const hyb_model* m, float* ms3);
+
+/* ---- block SpMM over many vectors ------------------------------------------ */
+
+/* Y = (H_b - c_b) X for n_vec float32 vectors of block b (c_b = lowest eigenvalue
+ * of the block), the SpMV of the Krylov step applied to a panel of vectors.
+ * Layout: X and Y are device float32 panels [n_vec / 16][dim][16]: 16 vectors are
+ * interleaved per row and each panel is one contiguous dim*16 chunk, so a panel
+ * streams from HBM in one pass.  n_vec must be a multiple of 16. */
+int hyb_block_spmm(hyb_model* m, int32_t block, int64_t n_vec, const float* X, float* Y, void* stream);
+
+/* ---- misc ------------------------------------------------------------------ */
+const char* hyb_last_error(void);
+const char* hyb_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HYB_H */

@@ -14,9 +14,10 @@ Each imaginary-time evolution inside block b is written out as the matrix
 function V_b diag(exp(-dtau (E_b - E0))) V_b^T from the block's eigen-
 decomposition.  Because |E_i> is an eigenstate, the two edge intervals reduce
 to the scalar exp(-(beta - tau_n + tau_1) (E_i - E0)) (step 3).  Energies are
-shifted by the ground energy E0 and the vector is renormalised after every
-step with its log-norm kept aside; these are exact rescalings that keep the
-float64 numbers in range, and -beta*E0 is added back at the end.
+shifted by the ground energy E0 (and, inside a propagation, by the block's
+own lowest eigenvalue), and the vector is renormalised after every step with
+its log-norm kept aside; these are exact rescalings that keep the float64
+numbers in range, and -beta*E0 is added back at the end.
 """
 from __future__ import annotations
 
@@ -89,6 +90,17 @@ class TraceOracle:
         Vb, Eb = self.spec.V[b], self.spec.E[b]
         return Vb @ (np.exp(-dtau * (Eb - self.spec.E0)) * (Vb.T @ v))
 
+    def propagate_log(self, b: int, v: np.ndarray, dtau: float):
+        """exp(-dtau (H_b - E0)) v as (unit vector, log of its norm).
+
+        The block's lowest eigenvalue is factored out before exponentiating so
+        that long intervals in high-lying blocks do not underflow."""
+        Vb, Eb = self.spec.V[b], self.spec.E[b]
+        emin = float(Eb.min())
+        y = Vb @ (np.exp(-dtau * (Eb - emin)) * (Vb.T @ v))
+        s = np.linalg.norm(y)
+        return y / s, np.log(s) - dtau * (emin - self.spec.E0)
+
     # -- one term of the outer sum ------------------------------------------
     def path(self, tau, flavor, dagger, beta: float, r: int):
         """(feasible, sign, log|t_r|) for retained state r (log includes -beta*E0)."""
@@ -112,12 +124,8 @@ class TraceOracle:
         b = b0
         for k in range(nops):
             if k > 0:
-                v = self.propagate(b, v, float(tau[k] - tau[k - 1]))
-                s = np.linalg.norm(v)
-                if s == 0.0:
-                    return True, 0, -np.inf
-                ell += np.log(s)
-                v = v / s
+                v, ls = self.propagate_log(b, v, float(tau[k] - tau[k - 1]))
+                ell += ls
             b, M = self.op_block(int(flavor[k]), int(dagger[k]), b)
             v = M @ v
             s = np.linalg.norm(v)

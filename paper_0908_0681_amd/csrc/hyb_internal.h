@@ -1,0 +1,85 @@
+// Internal declarations shared by the host model code and the HIP kernels of libhyb.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/hyb.h"
+
+namespace hyb {
+
+int set_error(int code, const char* fmt, ...);
+
+// Per-block metadata as seen by the device kernels (plain POD, uploaded as an array).
+struct BlockDev {
+  int32_t dim;        // number of states in the block
+  int32_t state_off;  // offset of the block's states in the packed state / row arrays
+  int32_t n_up, n_dn;
+  double shift;       // c_b: lowest eigenvalue of the block; kernels apply H_b - c_b
+};
+
+struct DeviceModel {
+  // basis
+  uint32_t* states = nullptr;   // [n_states] packed by block, ascending inside a block
+  int32_t* rank = nullptr;      // [n_states] state integer -> index inside its block
+  BlockDev* blocks = nullptr;   // [n_blocks]
+  // off-diagonal CSR over the packed rows (column = index inside the same block)
+  int32_t* rowptr = nullptr;    // [n_states + 1]
+  int32_t* col = nullptr;       // [nnz]
+  double* val64 = nullptr;      // [nnz]
+  float* val32 = nullptr;       // [nnz]
+  double* diag64 = nullptr;     // [n_states] h_ii - c_b
+  // retained set
+  int32_t* ret_block = nullptr; // [n_ret]
+  double* ret_energy = nullptr; // [n_ret]
+  int64_t* ret_off = nullptr;   // [n_ret] offset into ret_vec
+  double* ret_vec64 = nullptr;
+  float* ret_vec32 = nullptr;
+  // per-batch workspace
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  int device = -1;
+};
+
+}  // namespace hyb
+
+struct hyb_model {
+  hyb_model_params p{};
+  std::vector<double> eps;
+  int n_orb = 0, F = 0, n_blocks = 0, max_dim = 0;
+  int64_t n_states = 0;
+  // basis
+  std::vector<uint32_t> states;      // packed by block
+  std::vector<int32_t> rank;         // state -> index inside block
+  std::vector<int32_t> block_of;     // state -> block
+  std::vector<hyb::BlockDev> blocks;
+  // H_loc: diagonal + off-diagonal CSR (packed rows)
+  std::vector<double> diag;          // h_ii
+  std::vector<int32_t> rowptr, col;
+  std::vector<double> val;
+  // spectrum
+  std::vector<std::vector<double>> evals;   // per block, ascending
+  double E0 = 0.0;
+  // retained set
+  std::vector<int32_t> ret_block;
+  std::vector<double> ret_energy;
+  std::vector<int64_t> ret_off;
+  std::vector<double> ret_vec;
+  // device side
+  bool uploaded = false;
+  hyb::DeviceModel dev;
+  int variant = -1;         // trace kernel variant (-1 = automatic)
+  bool timing = false;
+  float last_ms[3] = {0, 0, 0};
+  void* events[4] = {nullptr, nullptr, nullptr, nullptr};
+};
+
+namespace hyb {
+// eigen.cpp
+// Dense symmetric eigensolver: eigenvalues (ascending) of the n x n row-major matrix a;
+// if n_vec > 0, also the eigenvectors of the n_vec lowest eigenvalues (columns of
+// vec, row-major n x n_vec).  Returns 0 or a negative error code.
+int sym_eig(int n, const double* a, double* evals, int n_vec, double* vec);
+void free_device(hyb_model* m);
+}  // namespace hyb

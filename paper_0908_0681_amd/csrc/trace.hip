@@ -1,0 +1,512 @@
+// Device side of libhyb: model upload, the batched trace (scan -> persistent
+// trace kernel -> signed log-sum), device parity hooks and kernel variants.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "hyb_internal.h"
+#include "trace_kernels.h"
+
+namespace hyb {
+
+#define HIP_TRY(expr)                                                                 \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return set_error(HYB_E_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));     \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// kernels
+// ---------------------------------------------------------------------------
+
+__global__ void k_init_counters(int32_t* c) {
+  if (threadIdx.x < 4) c[threadIdx.x] = 0;
+}
+
+__global__ void k_scan(TraceParams P) {
+  const int64_t id = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (id < int64_t(P.n_configs) * P.n_ret) scan_pair(P, id);
+}
+
+template <typename VT, int NT, int RPT, int MAXM>
+__global__ __launch_bounds__(NT) void k_trace(TraceParams P) {
+  using E = PathEngine<VT, NT, RPT, MAXM>;
+  __shared__ typename E::Smem S;
+  E eng(P, S);
+  eng.run_queue();
+}
+
+__global__ void k_reduce(TraceParams P, double* out_log, int8_t* out_sign, int32_t* out_steps,
+                         int32_t* out_sub, int32_t* out_feas) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < P.n_configs) reduce_config(P, c, out_log, out_sign, out_steps, out_sub, out_feas);
+}
+
+// Operator application on a batch of vectors (parity hook).
+__global__ void k_apply_op(const uint32_t* states, const int32_t* rank, BlockDev Bin, BlockDev Bout, int f,
+                           int dagger, int n_vec, const double* x, double* y) {
+  const int64_t id = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (id >= int64_t(n_vec) * Bout.dim) return;
+  const int v = int(id / Bout.dim), r = int(id - int64_t(v) * Bout.dim);
+  const uint32_t bit = 1u << f;
+  const uint32_t t = states[Bout.state_off + r];
+  const bool has = dagger ? ((t & bit) != 0u) : ((t & bit) == 0u);
+  double val = 0.0;
+  if (has) {
+    const uint32_t s = t ^ bit;
+    const double src = x[int64_t(v) * Bin.dim + rank[s]];
+    val = (__popc(s & (bit - 1u)) & 1) ? -src : src;
+  }
+  y[id] = val;
+}
+
+// Krylov propagation of a batch of vectors of one block (parity hook): one
+// workgroup per vector, same engine as the trace kernel.
+template <typename VT, int NT, int RPT, int MAXM>
+__global__ __launch_bounds__(NT) void k_propagate(TraceParams P, int block, const VT* x, const double* dtau,
+                                                  VT* y, double* log_scale, int32_t* steps_out) {
+  using E = PathEngine<VT, NT, RPT, MAXM>;
+  __shared__ typename E::Smem S;
+  E eng(P, S);
+  const BlockDev B = P.blocks[block];
+  const int v = blockIdx.x;
+  VT xr[RPT];
+  double part = 0.0;
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) {
+    const int r = eng.row(k);
+    xr[k] = (r < B.dim) ? x[int64_t(v) * B.dim + r] : VT(0);
+    part += to_d(xr[k]) * to_d(xr[k]);
+  }
+  const double n2 = eng.block_sum1(part);
+  double ell = 0.5 * log(n2);
+  const double inv = 1.0 / sqrt(n2);
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) xr[k] = static_cast<VT>(to_d(xr[k]) * inv);
+  int steps = 0, subs = 0;
+  eng.work = 0;
+  eng.nops_budget = 1;
+  const bool ok = eng.propagate(B, dtau[v], xr, ell, steps, subs);
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) {
+    const int r = eng.row(k);
+    if (r < B.dim) y[int64_t(v) * B.dim + r] = xr[k];
+  }
+  if (threadIdx.x == 0) {
+    log_scale[v] = ok ? ell : NAN;
+    if (steps_out) steps_out[v] = steps;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// kernel variants
+// ---------------------------------------------------------------------------
+
+struct Variant {
+  const char* name;
+  int fp64;   // 1: float64 vectors, 0: float32 (mixed)
+  int nt, rpt, maxm;
+  const void* trace_fn;
+  const void* prop_fn;
+};
+
+#define VARIANT(VT, NT, RPT, MAXM, NAME)                                                     \
+  {NAME, sizeof(VT) == 8, NT, RPT, MAXM, reinterpret_cast<const void*>(&k_trace<VT, NT, RPT, MAXM>), \
+   reinterpret_cast<const void*>(&k_propagate<VT, NT, RPT, MAXM>)}
+
+static const Variant kVariants[] = {
+    VARIANT(double, 64, 1, 12, "f64_nt64_r1_m12"),
+    VARIANT(double, 64, 2, 12, "f64_nt64_r2_m12"),
+    VARIANT(double, 64, 2, 16, "f64_nt64_r2_m16"),
+    VARIANT(double, 128, 1, 12, "f64_nt128_r1_m12"),
+    VARIANT(double, 256, 5, 12, "f64_nt256_r5_m12"),
+    VARIANT(float, 64, 2, 12, "f32_nt64_r2_m12"),
+    VARIANT(float, 256, 5, 12, "f32_nt256_r5_m12"),
+    VARIANT(float, 256, 5, 16, "f32_nt256_r5_m16"),
+    VARIANT(float, 512, 3, 12, "f32_nt512_r3_m12"),
+    VARIANT(float, 512, 3, 16, "f32_nt512_r3_m16"),
+};
+static const int kNumVariants = int(sizeof(kVariants) / sizeof(kVariants[0]));
+
+static bool variant_fits(const Variant& v, const hyb_model* m) {
+  const int want_fp64 = (m->p.precision == HYB_FP64) ? 1 : 0;
+  return v.fp64 == want_fp64 && v.nt * v.rpt >= m->max_dim;
+}
+
+// Automatic choice: the smallest workgroup that holds the largest block, with the
+// Lanczos register depth that covers krylov_max when possible.
+static int auto_variant(const hyb_model* m) {
+  int best = -1;
+  long best_cost = 0;
+  for (int i = 0; i < kNumVariants; ++i) {
+    const Variant& v = kVariants[i];
+    if (!variant_fits(v, m)) continue;
+    const long cost = long(v.nt) * v.rpt * 4 + (v.maxm >= m->p.krylov_max ? 0 : 1000000L) + v.maxm;
+    if (best < 0 || cost < best_cost) {
+      best = i;
+      best_cost = cost;
+    }
+  }
+  return best;
+}
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+
+template <typename T>
+static int dev_upload(T*& dst, const T* src, size_t n, hipStream_t s) {
+  if (n == 0) n = 1;
+  HIP_TRY(hipMalloc(reinterpret_cast<void**>(&dst), n * sizeof(T)));
+  if (src) HIP_TRY(hipMemcpyAsync(dst, src, n * sizeof(T), hipMemcpyHostToDevice, s));
+  return 0;
+}
+
+void free_device(hyb_model* m) {
+  if (!m || !m->uploaded) return;
+  DeviceModel& d = m->dev;
+  void* ptrs[] = {d.states, d.rank, d.blocks, d.rowptr, d.col, d.val64, d.val32, d.diag64,
+                  d.ret_block, d.ret_energy, d.ret_off, d.ret_vec64, d.ret_vec32, d.ws};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  for (void*& e : m->events)
+    if (e) {
+      (void)hipEventDestroy(reinterpret_cast<hipEvent_t>(e));
+      e = nullptr;
+    }
+  d = DeviceModel{};
+  m->uploaded = false;
+}
+
+static int ensure_ws(hyb_model* m, size_t bytes) {
+  if (m->dev.ws_bytes >= bytes) return 0;
+  if (m->dev.ws) {
+    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipFree(m->dev.ws));
+    m->dev.ws = nullptr;
+    m->dev.ws_bytes = 0;
+  }
+  const size_t want = std::max(bytes, size_t(1) << 20);
+  if (hipMalloc(&m->dev.ws, want) != hipSuccess) return set_error(HYB_E_OOM, "device workspace of %zu bytes", want);
+  m->dev.ws_bytes = want;
+  return 0;
+}
+
+static size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+static TraceParams base_params(const hyb_model* m) {
+  TraceParams P{};
+  const DeviceModel& d = m->dev;
+  P.states = d.states;
+  P.rank = d.rank;
+  P.blocks = d.blocks;
+  P.rowptr = d.rowptr;
+  P.col = d.col;
+  P.val64 = d.val64;
+  P.val32 = d.val32;
+  P.diag64 = d.diag64;
+  P.ret_block = d.ret_block;
+  P.ret_energy = d.ret_energy;
+  P.ret_off = d.ret_off;
+  P.ret_vec64 = d.ret_vec64;
+  P.ret_vec32 = d.ret_vec32;
+  P.n_orb = m->n_orb;
+  P.n_ret = int32_t(m->ret_block.size());
+  P.E0 = m->E0;
+  P.tol = m->p.krylov_tol;
+  P.kmax = m->p.krylov_max;
+  P.max_substeps = 32;
+  P.work_budget = 200000;
+  return P;
+}
+
+static int error_from_bits(int bits) {
+  if (bits & ERR_UNSORTED) return set_error(HYB_E_UNSORTED, "operator times not strictly increasing in [0, beta)");
+  if (bits & ERR_FLAVOR) return set_error(HYB_E_FLAVOR, "flavor or dagger out of range");
+  if (bits & ERR_NONFINITE) return set_error(HYB_E_NONFINITE, "non-finite value in the propagation");
+  if (bits & ERR_NOCONV) return set_error(HYB_E_NOCONV, "Krylov propagation exceeded the substep limit");
+  return 0;
+}
+
+}  // namespace hyb
+
+using namespace hyb;
+
+extern "C" {
+
+int hyb_model_upload(hyb_model* m, void* stream) {
+  if (!m) return set_error(HYB_E_ARG, "NULL model");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  free_device(m);
+  DeviceModel& d = m->dev;
+  HIP_TRY(hipGetDevice(&d.device));
+  int rc = 0;
+  std::vector<double> diag_shifted(m->n_states);
+  for (int b = 0; b < m->n_blocks; ++b)
+    for (int i = 0; i < m->blocks[b].dim; ++i) {
+      const int64_t g = m->blocks[b].state_off + i;
+      diag_shifted[g] = m->diag[g] - m->blocks[b].shift;
+    }
+  std::vector<float> val32(m->val.begin(), m->val.end());
+  std::vector<float> rv32(m->ret_vec.begin(), m->ret_vec.end());
+  m->uploaded = true;  // so that free_device releases partial uploads
+  if ((rc = dev_upload(d.states, m->states.data(), m->states.size(), s))) return rc;
+  if ((rc = dev_upload(d.rank, m->rank.data(), m->rank.size(), s))) return rc;
+  if ((rc = dev_upload(d.blocks, m->blocks.data(), m->blocks.size(), s))) return rc;
+  if ((rc = dev_upload(d.rowptr, m->rowptr.data(), m->rowptr.size(), s))) return rc;
+  if ((rc = dev_upload(d.col, m->col.data(), m->col.size(), s))) return rc;
+  if ((rc = dev_upload(d.val64, m->val.data(), m->val.size(), s))) return rc;
+  if ((rc = dev_upload(d.val32, val32.data(), val32.size(), s))) return rc;
+  if ((rc = dev_upload(d.diag64, diag_shifted.data(), diag_shifted.size(), s))) return rc;
+  if ((rc = dev_upload(d.ret_block, m->ret_block.data(), m->ret_block.size(), s))) return rc;
+  if ((rc = dev_upload(d.ret_energy, m->ret_energy.data(), m->ret_energy.size(), s))) return rc;
+  if ((rc = dev_upload(d.ret_off, m->ret_off.data(), m->ret_off.size(), s))) return rc;
+  if ((rc = dev_upload(d.ret_vec64, m->ret_vec.data(), m->ret_vec.size(), s))) return rc;
+  if ((rc = dev_upload(d.ret_vec32, rv32.data(), rv32.size(), s))) return rc;
+  // host staging vectors above are pageable: make sure the copies finished
+  HIP_TRY(hipStreamSynchronize(s));
+  for (void*& e : m->events) HIP_TRY(hipEventCreate(reinterpret_cast<hipEvent_t*>(&e)));
+  if (m->variant < 0 && auto_variant(m) < 0)
+    return set_error(HYB_E_ARG, "no trace kernel variant holds blocks of dimension %d", m->max_dim);
+  return HYB_OK;
+}
+
+int hyb_build_hloc(const hyb_model_params* p, void* stream, hyb_model** out) {
+  int rc = hyb_model_create(p, out);
+  if (rc) return rc;
+  rc = hyb_model_upload(*out, stream);
+  if (rc) {
+    hyb_model_destroy(*out);
+    *out = nullptr;
+  }
+  return rc;
+}
+
+int hyb_trace_variant_count(int32_t* n) {
+  if (!n) return set_error(HYB_E_ARG, "NULL argument");
+  *n = kNumVariants;
+  return HYB_OK;
+}
+
+int hyb_trace_variant_name(int32_t v, char* buf, size_t len) {
+  if (v < 0 || v >= kNumVariants || !buf || len == 0) return set_error(HYB_E_ARG, "bad variant / buffer");
+  std::snprintf(buf, len, "%s", kVariants[v].name);
+  return HYB_OK;
+}
+
+int hyb_set_trace_variant(hyb_model* m, int32_t v) {
+  if (!m) return set_error(HYB_E_ARG, "NULL model");
+  if (v < 0) {
+    m->variant = -1;
+    return HYB_OK;
+  }
+  if (v >= kNumVariants) return set_error(HYB_E_ARG, "unknown variant %d", v);
+  if (!variant_fits(kVariants[v], m))
+    return set_error(HYB_E_ARG, "variant %s does not fit this model (precision / block size)", kVariants[v].name);
+  m->variant = v;
+  return HYB_OK;
+}
+
+int hyb_get_trace_variant(const hyb_model* m, int32_t* v) {
+  if (!m || !v) return set_error(HYB_E_ARG, "NULL argument");
+  *v = m->variant >= 0 ? m->variant : auto_variant(m);
+  return HYB_OK;
+}
+
+int hyb_set_timing(hyb_model* m, int32_t on) {
+  if (!m) return set_error(HYB_E_ARG, "NULL model");
+  m->timing = on != 0;
+  return HYB_OK;
+}
+
+int hyb_last_timing(const hyb_model* m, float* ms) {
+  if (!m || !ms) return set_error(HYB_E_ARG, "NULL argument");
+  std::memcpy(ms, m->last_ms, sizeof m->last_ms);
+  return HYB_OK;
+}
+
+int hyb_trace_batch(hyb_model* m, const hyb_config_batch* cfg, double beta, hyb_trace_out* out, void* stream) {
+  if (!m || !cfg || !out) return set_error(HYB_E_ARG, "NULL argument");
+  if (!m->uploaded) return set_error(HYB_E_STATE, "model not uploaded to a device");
+  if (!(beta > 0.0) || !std::isfinite(beta)) return set_error(HYB_E_ARG, "beta must be positive and finite");
+  if (cfg->n_configs < 0) return set_error(HYB_E_ARG, "negative n_configs");
+  if (cfg->n_configs == 0) return HYB_OK;
+  if (!cfg->offsets || !out->log_abs || !out->sign) return set_error(HYB_E_ARG, "NULL array");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev != m->dev.device) return set_error(HYB_E_STATE, "model lives on device %d, current is %d", m->dev.device, dev);
+  const int vi = m->variant >= 0 ? m->variant : auto_variant(m);
+  const Variant& V = kVariants[vi];
+  const int nc = cfg->n_configs;
+  const int n_ret = int(m->ret_block.size());
+  const int64_t npairs = int64_t(nc) * n_ret;
+  if (npairs > (int64_t(1) << 31) - 1) return set_error(HYB_E_ARG, "too many (config, state) pairs");
+
+  // host configs: their size is needed for staging
+  int64_t n_ops = 0;
+  if (!cfg->on_device) {
+    if (cfg->offsets[0] != 0) return set_error(HYB_E_ARG, "offsets must start at 0");
+    for (int c = 0; c < nc; ++c)
+      if (cfg->offsets[c + 1] < cfg->offsets[c]) return set_error(HYB_E_ARG, "offsets must not decrease");
+    n_ops = cfg->offsets[nc];
+  }
+  // workspace layout
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align_up(off + bytes);
+    return o;
+  };
+  const size_t o_cnt = take(4 * sizeof(int32_t));
+  const size_t o_work = take(npairs * sizeof(int32_t));
+  const size_t o_psign = take(npairs * sizeof(int8_t));
+  const size_t o_plog = take(npairs * sizeof(double));
+  const size_t o_psteps = take(npairs * sizeof(int32_t));
+  const size_t o_psub = take(npairs * sizeof(int32_t));
+  size_t o_offs = 0, o_tau = 0, o_fl = 0, o_dg = 0;
+  if (!cfg->on_device) {
+    o_offs = take((nc + 1) * sizeof(int64_t));
+    o_tau = take(std::max<int64_t>(n_ops, 1) * sizeof(double));
+    o_fl = take(std::max<int64_t>(n_ops, 1) * sizeof(int16_t));
+    o_dg = take(std::max<int64_t>(n_ops, 1) * sizeof(int8_t));
+  }
+  size_t o_olog = 0, o_osign = 0, o_osteps = 0, o_osub = 0, o_ofeas = 0;
+  if (!out->on_device) {
+    o_olog = take(nc * sizeof(double));
+    o_osign = take(nc * sizeof(int8_t));
+    o_osteps = take(nc * sizeof(int32_t));
+    o_osub = take(nc * sizeof(int32_t));
+    o_ofeas = take(nc * sizeof(int32_t));
+  }
+  int rc = ensure_ws(m, off);
+  if (rc) return rc;
+  char* ws = static_cast<char*>(m->dev.ws);
+
+  TraceParams P = base_params(m);
+  P.n_configs = nc;
+  P.n_pairs = int32_t(npairs);
+  P.beta = beta;
+  P.counters = reinterpret_cast<int32_t*>(ws + o_cnt);
+  P.work = reinterpret_cast<int32_t*>(ws + o_work);
+  P.p_sign = reinterpret_cast<int8_t*>(ws + o_psign);
+  P.p_log = reinterpret_cast<double*>(ws + o_plog);
+  P.p_steps = reinterpret_cast<int32_t*>(ws + o_psteps);
+  P.p_sub = reinterpret_cast<int32_t*>(ws + o_psub);
+  if (cfg->on_device) {
+    P.offsets = cfg->offsets;
+    P.tau = cfg->tau;
+    P.flavor = cfg->flavor;
+    P.dagger = cfg->dagger;
+  } else {
+    P.offsets = reinterpret_cast<int64_t*>(ws + o_offs);
+    P.tau = reinterpret_cast<double*>(ws + o_tau);
+    P.flavor = reinterpret_cast<int16_t*>(ws + o_fl);
+    P.dagger = reinterpret_cast<int8_t*>(ws + o_dg);
+    HIP_TRY(hipMemcpyAsync(const_cast<int64_t*>(P.offsets), cfg->offsets, (nc + 1) * sizeof(int64_t),
+                           hipMemcpyHostToDevice, s));
+    if (n_ops > 0) {
+      if (!cfg->tau || !cfg->flavor || !cfg->dagger) return set_error(HYB_E_ARG, "NULL operator array");
+      HIP_TRY(hipMemcpyAsync(const_cast<double*>(P.tau), cfg->tau, n_ops * sizeof(double), hipMemcpyHostToDevice, s));
+      HIP_TRY(hipMemcpyAsync(const_cast<int16_t*>(P.flavor), cfg->flavor, n_ops * sizeof(int16_t),
+                             hipMemcpyHostToDevice, s));
+      HIP_TRY(hipMemcpyAsync(const_cast<int8_t*>(P.dagger), cfg->dagger, n_ops * sizeof(int8_t),
+                             hipMemcpyHostToDevice, s));
+    }
+  }
+  double* d_log = out->on_device ? out->log_abs : reinterpret_cast<double*>(ws + o_olog);
+  int8_t* d_sign = out->on_device ? out->sign : reinterpret_cast<int8_t*>(ws + o_osign);
+  int32_t* d_steps = out->on_device ? out->krylov_steps : reinterpret_cast<int32_t*>(ws + o_osteps);
+  int32_t* d_sub = out->on_device ? out->substeps : reinterpret_cast<int32_t*>(ws + o_osub);
+  int32_t* d_feas = out->on_device ? out->feasible_paths : reinterpret_cast<int32_t*>(ws + o_ofeas);
+
+  hipEvent_t ev[4];
+  for (int i = 0; i < 4; ++i) ev[i] = reinterpret_cast<hipEvent_t>(m->events[i]);
+  k_init_counters<<<1, 64, 0, s>>>(P.counters);
+  if (m->timing) HIP_TRY(hipEventRecord(ev[0], s));
+  const int scan_threads = 256;
+  k_scan<<<unsigned((npairs + scan_threads - 1) / scan_threads), scan_threads, 0, s>>>(P);
+  if (m->timing) HIP_TRY(hipEventRecord(ev[1], s));
+  // persistent grid: as many workgroups as can be resident, capped by the pair count
+  int per_cu = 0;
+  HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, V.trace_fn, V.nt, 0));
+  int n_cu = 0;
+  HIP_TRY(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+  const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(npairs, int64_t(std::max(per_cu, 1)) * n_cu));
+  void* args[] = {&P};
+  HIP_TRY(hipLaunchKernel(V.trace_fn, dim3(unsigned(grid)), dim3(V.nt), args, 0, s));
+  if (m->timing) HIP_TRY(hipEventRecord(ev[2], s));
+  k_reduce<<<(nc + 255) / 256, 256, 0, s>>>(P, d_log, d_sign, d_steps, d_sub, d_feas);
+  if (m->timing) HIP_TRY(hipEventRecord(ev[3], s));
+  HIP_TRY(hipGetLastError());
+  int32_t flags = 0;
+  HIP_TRY(hipMemcpyAsync(&flags, P.counters + 2, sizeof flags, hipMemcpyDeviceToHost, s));
+  if (!out->on_device) {
+    HIP_TRY(hipMemcpyAsync(out->log_abs, d_log, nc * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(out->sign, d_sign, nc * sizeof(int8_t), hipMemcpyDeviceToHost, s));
+    if (out->krylov_steps)
+      HIP_TRY(hipMemcpyAsync(out->krylov_steps, d_steps, nc * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    if (out->substeps) HIP_TRY(hipMemcpyAsync(out->substeps, d_sub, nc * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    if (out->feasible_paths)
+      HIP_TRY(hipMemcpyAsync(out->feasible_paths, d_feas, nc * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  if (m->timing) {
+    HIP_TRY(hipEventElapsedTime(&m->last_ms[0], ev[0], ev[1]));
+    HIP_TRY(hipEventElapsedTime(&m->last_ms[1], ev[1], ev[2]));
+    HIP_TRY(hipEventElapsedTime(&m->last_ms[2], ev[2], ev[3]));
+  }
+  return error_from_bits(flags);
+}
+
+int hyb_apply_op_device(hyb_model* m, int32_t f, int32_t dagger, int32_t bin, int32_t n_vec, const double* x,
+                        double* y, int32_t* bout, void* stream) {
+  if (!m || !x || !y || !bout) return set_error(HYB_E_ARG, "NULL argument");
+  if (!m->uploaded) return set_error(HYB_E_STATE, "model not uploaded");
+  if (f < 0 || f >= m->F || (dagger != 0 && dagger != 1)) return set_error(HYB_E_FLAVOR, "bad operator");
+  if (bin < 0 || bin >= m->n_blocks || n_vec < 0) return set_error(HYB_E_ARG, "bad block / count");
+  const BlockDev& B = m->blocks[bin];
+  int nu = B.n_up, nd = B.n_dn;
+  if (f < m->n_orb) nu += dagger ? 1 : -1; else nd += dagger ? 1 : -1;
+  if (nu < 0 || nu > m->n_orb || nd < 0 || nd > m->n_orb) {
+    *bout = -1;
+    return HYB_OK;
+  }
+  const int bt = nd * (m->n_orb + 1) + nu;
+  *bout = bt;
+  const int64_t total = int64_t(n_vec) * m->blocks[bt].dim;
+  if (total == 0) return HYB_OK;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  k_apply_op<<<unsigned((total + 255) / 256), 256, 0, s>>>(m->dev.states, m->dev.rank, B, m->blocks[bt], f, dagger,
+                                                           n_vec, x, y);
+  HIP_TRY(hipGetLastError());
+  return HYB_OK;
+}
+
+int hyb_propagate_device(hyb_model* m, int32_t block, int32_t n_vec, const void* x, const double* dtau, void* y,
+                         double* log_scale, int32_t* steps, void* stream) {
+  if (!m || !x || !dtau || !y || !log_scale) return set_error(HYB_E_ARG, "NULL argument");
+  if (!m->uploaded) return set_error(HYB_E_STATE, "model not uploaded");
+  if (block < 0 || block >= m->n_blocks || n_vec < 0) return set_error(HYB_E_ARG, "bad block / count");
+  if (m->blocks[block].dim == 0 || n_vec == 0) return HYB_OK;
+  const int vi = m->variant >= 0 ? m->variant : auto_variant(m);
+  const Variant& V = kVariants[vi];
+  int rc = ensure_ws(m, 256);
+  if (rc) return rc;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  TraceParams P = base_params(m);
+  P.counters = static_cast<int32_t*>(m->dev.ws);
+  k_init_counters<<<1, 64, 0, s>>>(P.counters);
+  void* args[] = {&P, &block, (void*)&x, (void*)&dtau, &y, &log_scale, &steps};
+  HIP_TRY(hipLaunchKernel(V.prop_fn, dim3(unsigned(n_vec)), dim3(V.nt), args, 0, s));
+  int32_t flags = 0;
+  HIP_TRY(hipMemcpyAsync(&flags, P.counters + 2, sizeof flags, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return error_from_bits(flags);
+}
+
+}  // extern "C"

@@ -1,0 +1,657 @@
+// Device code of the Krylov trace (gfx950, wave64).
+//
+// One workgroup evaluates one (configuration, retained state) path at a time and
+// pulls the next path from a device work queue (persistent launch).  The path's
+// vector lives in registers, RPT rows per thread (row = tid + k*NT); the Lanczos
+// basis V_0..V_m lives in registers too.  LDS holds only the vector being
+// gathered (operator application, SpMV) and the reduction partials.
+//
+// Steps (Sec. III): the retained eigenstate enters with the scalar phase of the
+// two edge intervals (step 3); each operator is a signed gather between blocks
+// (step 4); each interval is a Lanczos/Krylov propagation with an a-posteriori
+// stopping rule (step 5); the overlap with <E_i| closes the path (step 7); the
+// signed log-sum over R is a separate kernel (step 8).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+#include "hyb_internal.h"
+
+namespace hyb {
+
+enum : int32_t { ERR_UNSORTED = 1, ERR_FLAVOR = 2, ERR_NOCONV = 4, ERR_NONFINITE = 8 };
+
+struct TraceParams {
+  // model
+  const uint32_t* states;
+  const int32_t* rank;
+  const BlockDev* blocks;
+  const int32_t* rowptr;
+  const int32_t* col;
+  const double* val64;
+  const float* val32;
+  const double* diag64;
+  const int32_t* ret_block;
+  const double* ret_energy;
+  const int64_t* ret_off;
+  const double* ret_vec64;
+  const float* ret_vec32;
+  int32_t n_orb, n_ret;
+  double E0;
+  // configurations
+  int32_t n_configs;
+  const int64_t* offsets;
+  const double* tau;
+  const int16_t* flavor;
+  const int8_t* dagger;
+  double beta;
+  // work queue and per-path results (path id = config * n_ret + r)
+  int32_t* work;
+  int32_t* counters;  // [0] queued paths, [1] next ticket, [2] error bits
+  int8_t* p_sign;
+  double* p_log;
+  int32_t* p_steps;
+  int32_t* p_sub;
+  // Krylov settings
+  double tol;
+  int32_t kmax;
+  int32_t max_substeps;
+  int32_t n_pairs;     // n_configs * n_ret
+  int32_t work_budget; // QR sweeps allowed per path before it is abandoned
+};
+
+// ---------------------------------------------------------------------------
+// wavefront reductions (DPP inside rows of 16 lanes, then readlane)
+// ---------------------------------------------------------------------------
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  int lo = __double2loint(v), hi = __double2hiint(v);
+  lo = __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xF, 0xF, false);
+  hi = __builtin_amdgcn_update_dpp(0, hi, CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+  int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over the 64 lanes; every lane receives the same (bitwise) result.
+__device__ __forceinline__ double wave_sum(double x) {
+  x += dpp_d<0xB1>(x);   // quad_perm [1,0,3,2]
+  x += dpp_d<0x4E>(x);   // quad_perm [2,3,0,1]
+  x += dpp_d<0x141>(x);  // row_half_mirror
+  x += dpp_d<0x140>(x);  // row_mirror: every lane holds its 16-lane row sum
+  return (readlane_d(x, 0) + readlane_d(x, 16)) + (readlane_d(x, 32) + readlane_d(x, 48));
+}
+
+template <typename VT>
+__device__ __forceinline__ double to_d(VT x) { return static_cast<double>(x); }
+
+// ---------------------------------------------------------------------------
+// the per-workgroup path evaluator
+// ---------------------------------------------------------------------------
+
+template <typename VT, int NT, int RPT, int MAXM>
+struct PathEngine {
+  static constexpr int NW = NT / 64;
+  static constexpr int NRED = MAXM + 2;  // partial sums per reduction round
+  static constexpr int QLD = MAXM + 1;   // padded row length of Q in LDS
+
+  // Tridiagonal work space of one wavefront (uniform values; every wave of the
+  // workgroup keeps its own copy so that no extra barrier is needed).
+  struct Small {
+    double alpha[MAXM], beta[MAXM];  // Lanczos T_m
+    double a[2][MAXM], b[2][MAXM];   // QR snapshot / output buffers
+    double q[MAXM * QLD];            // eigenvectors, row r = component r
+    int cur;                         // buffer holding the eigenvalues
+  };
+  struct Smem {
+    VT vec[NT * RPT];
+    double red[2][NW][NRED];
+    Small small[NW];
+    int ticket, nwork;
+  };
+
+  const TraceParams& P;
+  Smem& S;
+  const int tid, lane, wid;
+  int rbuf = 0;
+
+  __device__ PathEngine(const TraceParams& p, Smem& s)
+      : P(p), S(s), tid(threadIdx.x), lane(threadIdx.x & 63), wid(threadIdx.x >> 6) {}
+
+  __device__ __forceinline__ const VT* ret_vec() const {
+    if constexpr (sizeof(VT) == 8) return reinterpret_cast<const VT*>(P.ret_vec64);
+    else return reinterpret_cast<const VT*>(P.ret_vec32);
+  }
+  __device__ __forceinline__ VT offval(int j) const {
+    if constexpr (sizeof(VT) == 8) return static_cast<VT>(P.val64[j]);
+    else return static_cast<VT>(P.val32[j]);
+  }
+
+  // Orders this wave's LDS traffic (all lanes of a wave run in lock step).
+  __device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+
+  // Workgroup sum of kact (<= K) per-thread partials; all threads get the totals
+  // in a fixed summation order.
+  template <int K>
+  __device__ __forceinline__ void block_sum(double (&v)[K], int kact) {
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+      if (k < kact) v[k] = wave_sum(v[k]);
+    if constexpr (NW > 1) {
+      if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+          if (k < kact) S.red[rbuf][wid][k] = v[k];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        if (k < kact) {
+          double s = 0.0;
+#pragma unroll
+          for (int w = 0; w < NW; ++w) s += S.red[rbuf][w][k];
+          v[k] = s;
+        }
+      }
+      rbuf ^= 1;
+    }
+  }
+
+  __device__ __forceinline__ double block_sum1(double x) {
+    double v[1] = {x};
+    block_sum<1>(v, 1);
+    return v[0];
+  }
+
+  __device__ __forceinline__ int row(int k) const { return tid + k * NT; }
+
+  // y = (H_b - c_b) x for the rows owned by this thread.  x is staged in LDS.
+  __device__ __forceinline__ void spmv(const BlockDev& B, const VT (&x)[RPT], VT (&y)[RPT]) {
+#pragma unroll
+    for (int k = 0; k < RPT; ++k)
+      if (row(k) < B.dim) S.vec[row(k)] = x[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+      const int r = row(k);
+      if (r < B.dim) {
+        const int g = B.state_off + r;
+        const int j0 = P.rowptr[g], j1 = P.rowptr[g + 1];
+        VT acc = VT(0);
+        for (int j = j0; j < j1; ++j) acc += offval(j) * S.vec[P.col[j]];
+        y[k] = static_cast<VT>(P.diag64[g] * to_d(x[k]) + to_d(acc));
+      } else {
+        y[k] = VT(0);
+      }
+    }
+    __syncthreads();  // S.vec is rewritten by the next staging
+  }
+
+  // x <- O x with O = c_f (dagger 0) or c_f^dag (dagger 1), block B -> Bt.
+  // Returns the squared norm of the result.
+  __device__ __forceinline__ double apply_op(const BlockDev& B, const BlockDev& Bt, int f, int dagger,
+                                             VT (&x)[RPT]) {
+#pragma unroll
+    for (int k = 0; k < RPT; ++k)
+      if (row(k) < B.dim) S.vec[row(k)] = x[k];
+    __syncthreads();
+    const uint32_t bit = 1u << f;
+    double nrm = 0.0;
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+      const int r = row(k);
+      VT val = VT(0);
+      if (r < Bt.dim) {
+        const uint32_t t = P.states[Bt.state_off + r];
+        // source state s with O|s> ~ |t>: creator needs bit f set in t, annihilator unset
+        const bool has = dagger ? ((t & bit) != 0u) : ((t & bit) == 0u);
+        if (has) {
+          const uint32_t s = t ^ bit;
+          const VT src = S.vec[P.rank[s]];
+          val = (__popc(s & (bit - 1u)) & 1) ? -src : src;
+        }
+      }
+      x[k] = val;
+      nrm += to_d(val) * to_d(val);
+    }
+    __syncthreads();  // S.vec may be rewritten right after
+    return block_sum1(nrm);
+  }
+
+  // Eigendecomposition of the m x m symmetric tridiagonal T = (alpha, beta) of this
+  // wave by implicit QR sweeps with the Wilkinson shift (the host eigensolver's
+  // algorithm).  Every lane reads the same snapshot of T (buffer `in`) and takes the
+  // same decisions; lane 0 writes the swept T into the other buffer, which becomes
+  // the snapshot after a wave synchronisation, so no lane ever reads an entry while
+  // another writes it.  Lane r (< m) keeps row r of the eigenvector matrix in W.q.
+  // On return the eigenvalues are in W.a[W.cur][0..m).  Returns the sweep count.
+  __device__ int small_eig(Small& W, int m) {
+    if (lane < m) {
+      W.a[0][lane] = W.alpha[lane];
+      W.b[0][lane] = (lane + 1 < m) ? W.beta[lane] : 0.0;
+      for (int c = 0; c < m; ++c) W.q[lane * QLD + c] = (c == lane) ? 1.0 : 0.0;
+    }
+    int in = 0;
+    wave_sync();
+    const double eps = 2.220446049250313e-16;
+    int q = m - 1;
+    int sweeps = 0;
+    for (; sweeps < 30 * MAXM; ++sweeps) {
+      // decisions from the snapshot: trailing unreduced block [p, q]
+      const double* A = W.a[in];
+      const double* Bv = W.b[in];
+      auto negligible = [&](int i) {
+        return fabs(Bv[i]) <= eps * (fabs(A[i]) + fabs(A[i + 1]));
+      };
+      while (q > 0 && negligible(q - 1)) --q;
+      if (q == 0) break;
+      int p = q - 1;
+      while (p > 0 && !negligible(p - 1)) --p;
+      // copy the snapshot into the output buffer with negligible couplings zeroed
+      const int out = in ^ 1;
+      if (lane < m) {
+        W.a[out][lane] = A[lane];
+        W.b[out][lane] = (lane + 1 < m && !negligible(lane)) ? Bv[lane] : 0.0;
+      }
+      wave_sync();
+      const double aq1 = A[q - 1], aq = A[q], bq = Bv[q - 1];
+      const double dd = 0.5 * (aq1 - aq);
+      const double den = dd + (dd >= 0.0 ? 1.0 : -1.0) * hypot(dd, bq);
+      const double mu = aq - bq * bq / den;
+      double x = A[p] - mu, z = Bv[p];
+      double ak = A[p], bk = Bv[p];
+      for (int k = p; k < q; ++k) {
+        const double ak1 = A[k + 1];
+        const double bk1 = (k + 1 < q) ? Bv[k + 1] : 0.0;
+        const double r = hypot(x, z);
+        double c = 1.0, s = 0.0;
+        if (r != 0.0) {
+          c = x / r;
+          s = z / r;
+        }
+        const double na = c * c * ak + 2.0 * c * s * bk + s * s * ak1;
+        const double na1 = s * s * ak - 2.0 * c * s * bk + c * c * ak1;
+        const double nb = c * s * (ak1 - ak) + (c * c - s * s) * bk;
+        const double bulge = s * bk1;
+        const double nb1 = c * bk1;
+        if (lane == 0) {
+          if (k > p) W.b[out][k - 1] = r;
+          W.a[out][k] = na;
+          W.a[out][k + 1] = na1;
+          W.b[out][k] = nb;
+          if (k + 1 < q) W.b[out][k + 1] = nb1;
+        }
+        if (lane < m) {
+          double* qr = &W.q[lane * QLD];
+          const double qk = qr[k], qk1 = qr[k + 1];
+          qr[k] = c * qk + s * qk1;
+          qr[k + 1] = -s * qk + c * qk1;
+        }
+        ak = na1;
+        bk = nb1;
+        x = nb;
+        z = bulge;
+      }
+      wave_sync();  // the swept T becomes the next snapshot
+      in = out;
+    }
+    W.cur = in;
+    wave_sync();
+    return sweeps;
+  }
+
+  int work = 0;         // QR sweeps spent on the current path
+  int nops_budget = 1;  // operators of the current path (sizes the step budget)
+
+  __device__ bool propagate(const BlockDev& B, double dtau, VT (&x)[RPT], double& ell, int& steps,
+                            int& subs) {
+    Small& W = S.small[wid];
+    const int kmax = (P.kmax < MAXM) ? P.kmax : MAXM;
+    const double shift = B.shift - P.E0;  // H - E0 = (H - c_b) + (c_b - E0)
+    constexpr double EPSV = (sizeof(VT) == 8) ? 2.220446049250313e-16 : 5.9604644775390625e-08;
+    double remaining = dtau;
+    VT V[MAXM + 1][RPT];
+    for (int nsub = 0; remaining > 0.0; ++nsub) {
+      if (nsub > P.max_substeps) {
+        atomicOr(&P.counters[2], ERR_NOCONV);
+        return false;
+      }
+#pragma unroll
+      for (int k = 0; k < RPT; ++k) V[0][k] = x[k];
+      int m = 0;
+      double tau_used = remaining, theta_min = 0.0, ynorm = 1.0, yv = 0.0, tscale = 0.0;
+      for (int j = 0; j < kmax; ++j) {
+        VT vj[RPT], w[RPT];
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) vj[k] = V[0][k];
+#pragma unroll
+        for (int i = 1; i < MAXM; ++i)
+          if (i == j) {
+#pragma unroll
+            for (int k = 0; k < RPT; ++k) vj[k] = V[i][k];
+          }
+        spmv(B, vj, w);
+        // classical Gram-Schmidt twice against V_0..V_j; the second round also
+        // reduces ||w||^2 so that beta_j needs no extra round
+        double hj;
+        {
+          double h[NRED];
+#pragma unroll
+          for (int i = 0; i < NRED; ++i) h[i] = 0.0;
+#pragma unroll
+          for (int i = 0; i < MAXM; ++i)
+            if (i <= j) {
+#pragma unroll
+              for (int k = 0; k < RPT; ++k) h[i] += to_d(V[i][k]) * to_d(w[k]);
+            }
+          block_sum<NRED>(h, j + 1);
+#pragma unroll
+          for (int k = 0; k < RPT; ++k) {
+            double t = to_d(w[k]);
+#pragma unroll
+            for (int i = 0; i < MAXM; ++i)
+              if (i <= j) t -= h[i] * to_d(V[i][k]);
+            w[k] = static_cast<VT>(t);
+          }
+          hj = h[0];
+#pragma unroll
+          for (int i = 1; i < MAXM; ++i)
+            if (i == j) hj = h[i];
+        }
+        double bj;
+        {
+          double h[NRED];
+#pragma unroll
+          for (int i = 0; i < NRED; ++i) h[i] = 0.0;
+          double wn = 0.0;
+#pragma unroll
+          for (int k = 0; k < RPT; ++k) {
+            const double wd = to_d(w[k]);
+#pragma unroll
+            for (int i = 0; i < MAXM; ++i)
+              if (i <= j) h[i] += to_d(V[i][k]) * wd;
+            wn += wd * wd;
+          }
+#pragma unroll
+          for (int i = 1; i < NRED; ++i)
+            if (i == j + 1) h[i] = wn;
+          block_sum<NRED>(h, j + 2);
+          double wn2 = 0.0, corr = 0.0;
+#pragma unroll
+          for (int i = 1; i < NRED; ++i)
+            if (i == j + 1) wn2 = h[i];
+#pragma unroll
+          for (int i = 0; i < MAXM; ++i)
+            if (i <= j) corr += h[i] * h[i];
+#pragma unroll
+          for (int k = 0; k < RPT; ++k) {
+            double t = to_d(w[k]);
+#pragma unroll
+            for (int i = 0; i < MAXM; ++i)
+              if (i <= j) t -= h[i] * to_d(V[i][k]);
+            w[k] = static_cast<VT>(t);
+          }
+          double h2j = h[0];
+#pragma unroll
+          for (int i = 1; i < MAXM; ++i)
+            if (i == j) h2j = h[i];
+          hj += h2j;
+          const double b2 = wn2 - corr;
+          bj = b2 > 0.0 ? sqrt(b2) : 0.0;
+        }
+        if (lane == 0) {
+          W.alpha[j] = hj;
+          W.beta[j] = bj;
+        }
+        wave_sync();
+        tscale = fmax(tscale, fabs(hj) + bj);
+        ++steps;
+        // small problem: eigendecomposition of T_{j+1}, then
+        // y = Q exp(-tau (Theta - theta_min)) Q^T e_1 and the a-posteriori estimate
+        work += small_eig(W, j + 1);
+        if (work > P.work_budget || steps > 40 * nops_budget + 400) {
+          // far beyond any healthy propagation: report instead of grinding on
+          atomicOr(&P.counters[2], ERR_NOCONV);
+          return false;
+        }
+        const double* theta = W.a[W.cur];
+        theta_min = theta[0];
+        for (int i = 1; i <= j; ++i) theta_min = fmin(theta_min, theta[i]);
+        const double breakdown = 4.0 * EPSV * (tscale + 1e-300);
+        const bool last = (j + 1 >= kmax);
+        double tau_try = remaining;
+        bool ok = false;
+        double ylane = 0.0;
+        for (int attempt = 0; attempt < 60; ++attempt) {
+          double yn2 = 0.0;
+          ylane = 0.0;
+          for (int i = 0; i <= j; ++i) {
+            const double wk = exp(-tau_try * (theta[i] - theta_min)) * W.q[i];  // Q[0][i]
+            yn2 += wk * wk;
+            if (lane <= j) ylane += W.q[lane * QLD + i] * wk;
+          }
+          const double ylast = readlane_d(ylane, j);
+          ynorm = sqrt(yn2);
+          const double est = bj * fabs(ylast) / ynorm;
+          ok = (est <= P.tol) || (bj <= breakdown);
+          if (ok || !last) break;
+          tau_try *= 0.5;  // depth cap reached: shorten the substep
+        }
+        if (ok) {
+          m = j + 1;
+          tau_used = tau_try;
+          yv = ylane;
+          break;
+        }
+        if (last) {
+          atomicOr(&P.counters[2], ERR_NOCONV);
+          return false;
+        }
+        const double inv = 1.0 / bj;
+#pragma unroll
+        for (int i = 1; i <= MAXM; ++i)
+          if (i == j + 1) {
+#pragma unroll
+            for (int k = 0; k < RPT; ++k) V[i][k] = static_cast<VT>(to_d(w[k]) * inv);
+          }
+      }
+      // recombination x = V_m y / ||y||
+      const double inv = 1.0 / ynorm;
+#pragma unroll
+      for (int k = 0; k < RPT; ++k) {
+        double t = 0.0;
+#pragma unroll
+        for (int i = 0; i < MAXM; ++i)
+          if (i < m) t += readlane_d(yv, i) * to_d(V[i][k]);
+        x[k] = static_cast<VT>(t * inv);
+      }
+      ell += -tau_used * (shift + theta_min) + log(ynorm);
+      remaining -= tau_used;
+      if (remaining > 0.0) ++subs;
+    }
+    return true;
+  }
+
+  // Evaluates path id = config * n_ret + r and stores sign / log / diagnostics.
+  __device__ void run_path(int id) {
+    const int c = id / P.n_ret, r = id - c * P.n_ret;
+    const int64_t o0 = P.offsets[c], o1 = P.offsets[c + 1];
+    const int nops = int(o1 - o0);
+    const double Ei = P.ret_energy[r];
+    int steps = 0, subs = 0;
+    work = 0;
+    nops_budget = nops;
+    if (nops == 0) {
+      if (tid == 0) {
+        P.p_sign[id] = 1;
+        P.p_log[id] = -P.beta * Ei;
+        P.p_steps[id] = 0;
+        P.p_sub[id] = 0;
+      }
+      return;
+    }
+    const double* tau = P.tau + o0;
+    double ell = -(P.beta - tau[nops - 1] + tau[0]) * (Ei - P.E0);
+    const VT* e_i = ret_vec() + P.ret_off[r];
+    VT x[RPT];
+    BlockDev B = P.blocks[P.ret_block[r]];
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) x[k] = (row(k) < B.dim) ? e_i[row(k)] : VT(0);
+    bool ok = true, zero = false;
+    for (int k = 0; k < nops; ++k) {
+      if (k > 0) {
+        ok = propagate(B, tau[k] - tau[k - 1], x, ell, steps, subs);
+        if (!ok) break;
+      }
+      const int f = P.flavor[o0 + k];
+      const int dg = P.dagger[o0 + k] ? 1 : 0;
+      int nu = B.n_up, nd = B.n_dn;
+      if (f < P.n_orb) nu += dg ? 1 : -1; else nd += dg ? 1 : -1;
+      if (nu < 0 || nu > P.n_orb || nd < 0 || nd > P.n_orb) {  // excluded by the scan
+        ok = false;
+        break;
+      }
+      const BlockDev Bt = P.blocks[nd * (P.n_orb + 1) + nu];
+      const double n2 = apply_op(B, Bt, f, dg, x);
+      B = Bt;
+      if (!(n2 > 0.0)) {
+        if (n2 != 0.0) atomicOr(&P.counters[2], ERR_NONFINITE);
+        zero = true;
+        break;
+      }
+      if (!isfinite(n2)) {
+        atomicOr(&P.counters[2], ERR_NONFINITE);
+        ok = false;
+        break;
+      }
+      ell += 0.5 * log(n2);
+      const double inv = 1.0 / sqrt(n2);
+#pragma unroll
+      for (int q = 0; q < RPT; ++q) x[q] = static_cast<VT>(to_d(x[q]) * inv);
+    }
+    double ov = 0.0;
+    if (ok && !zero) {
+      double part = 0.0;
+#pragma unroll
+      for (int k = 0; k < RPT; ++k)
+        if (row(k) < B.dim) part += to_d(e_i[row(k)]) * to_d(x[k]);
+      ov = block_sum1(part);
+    }
+    if (tid == 0) {
+      if (!ok || zero || ov == 0.0) {
+        P.p_sign[id] = 0;
+        P.p_log[id] = -INFINITY;
+      } else {
+        P.p_sign[id] = ov > 0.0 ? 1 : -1;
+        P.p_log[id] = ell + log(fabs(ov)) - P.beta * P.E0;
+      }
+      P.p_steps[id] = steps;
+      P.p_sub[id] = subs;
+    }
+  }
+  // Persistent work loop: take tickets until the queue of feasible paths is empty.
+  // Tickets only grow, and no workgroup goes past n_pairs of them, so the loop
+  // ends for every workgroup whatever the queue holds.
+  __device__ void run_queue() {
+    for (;;) {
+      if (tid == 0) {
+        S.ticket = atomicAdd(&P.counters[1], 1);
+        S.nwork = __atomic_load_n(&P.counters[0], __ATOMIC_RELAXED);
+      }
+      __syncthreads();
+      const int t = S.ticket;
+      const int nwork = S.nwork;
+      __syncthreads();
+      if (t >= nwork || t >= P.n_pairs) break;
+      const int id = P.work[t];
+      if (id < 0 || id >= P.n_pairs) break;
+      run_path(id);
+    }
+  }
+};
+
+// Validates configurations and walks the (n_up, n_dn) sector path of every
+// (config, retained state) pair; queues the pairs whose path stays physical and
+// returns to its starting block (the others are structural zeros).
+__device__ inline void scan_pair(const TraceParams& P, int64_t id) {
+  const int c = int(id / P.n_ret), r = int(id - int64_t(c) * P.n_ret);
+  const int64_t o0 = P.offsets[c], o1 = P.offsets[c + 1];
+  int err = 0;
+  const BlockDev B0 = P.blocks[P.ret_block[r]];
+  int nu = B0.n_up, nd = B0.n_dn;
+  bool feas = true;
+  double prev = -1.0;
+  if (o1 < o0) err |= ERR_UNSORTED;
+  for (int64_t k = o0; k < o1; ++k) {
+    const double t = P.tau[k];
+    if (!(t >= 0.0) || !(t < P.beta) || !(t > prev)) err |= ERR_UNSORTED;
+    prev = t;
+    const int f = P.flavor[k];
+    const int dg = P.dagger[k];
+    if (f < 0 || f >= 2 * P.n_orb || (dg != 0 && dg != 1)) {
+      err |= ERR_FLAVOR;
+      continue;
+    }
+    const int step = dg ? 1 : -1;
+    if (f < P.n_orb) nu += step; else nd += step;
+    if (nu < 0 || nu > P.n_orb || nd < 0 || nd > P.n_orb) feas = false;
+  }
+  if (nu != B0.n_up || nd != B0.n_dn) feas = false;
+  if (err) feas = false;
+  P.p_sign[id] = 0;
+  P.p_log[id] = -INFINITY;
+  P.p_steps[id] = 0;
+  P.p_sub[id] = feas ? 0 : -1;
+  if (err && r == 0) atomicOr(&P.counters[2], err);
+  if (feas) {
+    const int slot = atomicAdd(&P.counters[0], 1);
+    P.work[slot] = int32_t(id);
+  }
+}
+
+// Signed log-sum over the retained states of every configuration (step 8),
+// in a fixed order so that repeated runs are bitwise identical.
+__device__ inline void reduce_config(const TraceParams& P, int c, double* out_log, int8_t* out_sign,
+                                     int32_t* out_steps, int32_t* out_sub, int32_t* out_feas) {
+  const int64_t base = int64_t(c) * P.n_ret;
+  double mx = -INFINITY;
+  int steps = 0, subs = 0, feas = 0;
+  for (int r = 0; r < P.n_ret; ++r) {
+    if (P.p_sign[base + r] != 0) mx = fmax(mx, P.p_log[base + r]);
+    steps += P.p_steps[base + r];
+    if (P.p_sub[base + r] >= 0) {
+      ++feas;
+      subs += P.p_sub[base + r];
+    }
+  }
+  int8_t sg = 0;
+  double lg = -INFINITY;
+  if (mx > -INFINITY) {
+    double s = 0.0;
+    for (int r = 0; r < P.n_ret; ++r) {
+      const int8_t q = P.p_sign[base + r];
+      if (q != 0) s += q * exp(P.p_log[base + r] - mx);
+    }
+    if (s != 0.0) {
+      sg = s > 0.0 ? 1 : -1;
+      lg = mx + log(fabs(s));
+    }
+  }
+  out_log[c] = lg;
+  out_sign[c] = sg;
+  if (out_steps) out_steps[c] = steps;
+  if (out_sub) out_sub[c] = subs;
+  if (out_feas) out_feas[c] = feas;
+}
+
+}  // namespace hyb

@@ -1,0 +1,308 @@
+"""Thin ctypes binding of libhyb (argument marshalling only).
+
+Every step of the trace runs in the library's HIP kernels; this module only
+converts numpy arrays / torch device tensors into pointers and sizes.  It
+refuses to run when libhyb.so is missing: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhyb.so")
+
+HYB_OK = 0
+ERRORS = {-1: "HYB_E_ARG", -2: "HYB_E_UNSORTED", -3: "HYB_E_FLAVOR", -4: "HYB_E_NOCONV",
+          -5: "HYB_E_NONFINITE", -6: "HYB_E_HIP", -7: "HYB_E_OOM", -8: "HYB_E_STATE"}
+HYB_CSR = 0
+HYB_FP64, HYB_MIXED = 0, 1
+
+
+class HybError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class ModelParamsC(C.Structure):
+    _fields_ = [("n_orb", C.c_int32), ("eps", C.POINTER(C.c_double)), ("U", C.c_double),
+                ("Up", C.c_double), ("J", C.c_double), ("J_sf", C.c_double), ("J_ph", C.c_double),
+                ("storage", C.c_int32), ("precision", C.c_int32), ("retain_window", C.c_double),
+                ("krylov_max", C.c_int32), ("krylov_tol", C.c_double)]
+
+
+class ModelInfoC(C.Structure):
+    _fields_ = [("n_orb", C.c_int32), ("n_flavors", C.c_int32), ("n_blocks", C.c_int32),
+                ("max_dim", C.c_int32), ("n_retained", C.c_int32), ("precision", C.c_int32),
+                ("n_states", C.c_int64), ("nnz_offdiag", C.c_int64), ("E0", C.c_double)]
+
+
+class ConfigBatchC(C.Structure):
+    _fields_ = [("n_configs", C.c_int32), ("offsets", C.c_void_p), ("tau", C.c_void_p),
+                ("flavor", C.c_void_p), ("dagger", C.c_void_p), ("on_device", C.c_int32)]
+
+
+class TraceOutC(C.Structure):
+    _fields_ = [("log_abs", C.c_void_p), ("sign", C.c_void_p), ("krylov_steps", C.c_void_p),
+                ("substeps", C.c_void_p), ("feasible_paths", C.c_void_p), ("on_device", C.c_int32)]
+
+
+# name -> (restype, argtypes)
+_P = C.c_void_p
+_SIGS = {
+    "hyb_model_create": (C.c_int, [C.POINTER(ModelParamsC), C.POINTER(_P)]),
+    "hyb_model_upload": (C.c_int, [_P, _P]),
+    "hyb_build_hloc": (C.c_int, [C.POINTER(ModelParamsC), _P, C.POINTER(_P)]),
+    "hyb_model_destroy": (None, [_P]),
+    "hyb_model_info": (C.c_int, [_P, C.POINTER(ModelInfoC)]),
+    "hyb_block_info": (C.c_int, [_P, C.c_int32, _P, _P, _P]),
+    "hyb_block_eigenvalues": (C.c_int, [_P, C.c_int32, _P]),
+    "hyb_basis_state": (C.c_int, [_P, C.c_int32, C.c_int32, _P]),
+    "hyb_basis_index": (C.c_int, [_P, C.c_uint32, _P, _P]),
+    "hyb_block_dense": (C.c_int, [_P, C.c_int32, _P]),
+    "hyb_retained": (C.c_int, [_P, _P, _P, _P]),
+    "hyb_apply_op": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32, _P, _P, _P]),
+    "hyb_apply_op_device": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, _P, _P, _P, _P]),
+    "hyb_propagate_device": (C.c_int, [_P, C.c_int32, C.c_int32, _P, _P, _P, _P, _P, _P]),
+    "hyb_trace_batch": (C.c_int, [_P, C.POINTER(ConfigBatchC), C.c_double, C.POINTER(TraceOutC), _P]),
+    "hyb_set_trace_variant": (C.c_int, [_P, C.c_int32]),
+    "hyb_get_trace_variant": (C.c_int, [_P, _P]),
+    "hyb_trace_variant_count": (C.c_int, [_P]),
+    "hyb_trace_variant_name": (C.c_int, [C.c_int32, C.c_char_p, C.c_size_t]),
+    "hyb_set_timing": (C.c_int, [_P, C.c_int32]),
+    "hyb_last_timing": (C.c_int, [_P, _P]),
+    "hyb_block_spmm": (C.c_int, [_P, C.c_int32, C.c_int64, _P, _P, _P]),
+    "hyb_last_error": (C.c_char_p, []),
+    "hyb_version": (C.c_char_p, []),
+}
+
+_lib = None
+_VERBOSE = os.environ.get("HYB_VERBOSE", "") not in ("", "0")
+
+
+def _log(msg):
+    if _VERBOSE:
+        print(f"[hyb] {msg}", flush=True)
+
+
+def lib():
+    """Loads libhyb.so (raises if it was not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: run paper_0908_0681_amd.build first")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return list(_SIGS)
+
+
+def _check(rc):
+    if rc != HYB_OK:
+        raise HybError(rc, lib().hyb_last_error().decode())
+
+
+def _ptr(a):
+    """Pointer of a numpy array or a torch tensor (host or device)."""
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        assert a.flags["C_CONTIGUOUS"]
+        return a.ctypes.data
+    return a.data_ptr()   # torch tensor
+
+
+def _stream(stream):
+    if stream is None:
+        try:
+            import torch
+            if torch.cuda.is_available():
+                return torch.cuda.current_stream().cuda_stream
+        except Exception:
+            pass
+        return None
+    return stream if isinstance(stream, int) else stream.cuda_stream
+
+
+@dataclass
+class TraceResult:
+    sign: np.ndarray
+    log_abs: np.ndarray
+    krylov_steps: np.ndarray
+    substeps: np.ndarray
+    feasible_paths: np.ndarray
+
+
+class Model:
+    """Owns a hyb_model handle."""
+
+    def __init__(self, params, precision="fp64", retain_window=1e-5, krylov_max=12,
+                 krylov_tol=None, upload=True, stream=None):
+        prec = {"fp64": HYB_FP64, "mixed": HYB_MIXED}[precision]
+        if krylov_tol is None:
+            krylov_tol = 1e-13 if prec == HYB_FP64 else 1e-7
+        self._eps = np.ascontiguousarray(params.eps, dtype=np.float64)
+        p = ModelParamsC(n_orb=params.n_orb, eps=self._eps.ctypes.data_as(C.POINTER(C.c_double)),
+                         U=params.U, Up=params.Up, J=params.J, J_sf=params.J_sf, J_ph=params.J_ph,
+                         storage=HYB_CSR, precision=prec, retain_window=retain_window,
+                         krylov_max=krylov_max, krylov_tol=krylov_tol)
+        h = C.c_void_p()
+        _check(lib().hyb_model_create(C.byref(p), C.byref(h)))
+        self.h = h
+        self.precision = precision
+        if upload:
+            self.upload(stream)
+
+    def upload(self, stream=None):
+        _check(lib().hyb_model_upload(self.h, _stream(stream)))
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().hyb_model_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- host information / parity hooks ------------------------------------
+    def info(self):
+        i = ModelInfoC()
+        _check(lib().hyb_model_info(self.h, C.byref(i)))
+        return {k: getattr(i, k) for k, _ in ModelInfoC._fields_}
+
+    def block_info(self, b):
+        d, n, e = C.c_int32(), C.c_int32(), C.c_double()
+        _check(lib().hyb_block_info(self.h, b, C.byref(d), C.byref(n), C.byref(e)))
+        return d.value, n.value, e.value
+
+    def block_eigenvalues(self, b):
+        d = self.block_info(b)[0]
+        e = np.zeros(d)
+        _check(lib().hyb_block_eigenvalues(self.h, b, _ptr(e)))
+        return e
+
+    def basis_state(self, b, i):
+        s = C.c_uint32()
+        _check(lib().hyb_basis_state(self.h, b, i, C.byref(s)))
+        return s.value
+
+    def basis_index(self, s):
+        b, i = C.c_int32(), C.c_int32()
+        _check(lib().hyb_basis_index(self.h, s, C.byref(b), C.byref(i)))
+        return b.value, i.value
+
+    def block_dense(self, b):
+        d = self.block_info(b)[0]
+        h = np.zeros((d, d))
+        _check(lib().hyb_block_dense(self.h, b, _ptr(h)))
+        return h
+
+    def retained(self):
+        n = self.info()["n_retained"]
+        blk = np.zeros(n, np.int32)
+        en = np.zeros(n)
+        _check(lib().hyb_retained(self.h, _ptr(blk), _ptr(en), None))
+        tot = sum(self.block_info(int(b))[0] for b in blk)
+        vec = np.zeros(max(tot, 1))
+        _check(lib().hyb_retained(self.h, None, None, _ptr(vec)))
+        return blk, en, vec[:tot]
+
+    def apply_op(self, f, dagger, b, x):
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        bo = C.c_int32()
+        y = np.zeros(max(self.info()["max_dim"], 1))
+        _check(lib().hyb_apply_op(self.h, f, dagger, b, _ptr(x), C.byref(bo), _ptr(y)))
+        if bo.value < 0:
+            return -1, None
+        return bo.value, y[: self.block_info(bo.value)[0]].copy()
+
+    # ---- device calls ---------------------------------------------------------
+    def apply_op_device(self, f, dagger, b, x, y, stream=None):
+        """x, y: device tensors [n_vec, dim] float64."""
+        bo = C.c_int32()
+        _check(lib().hyb_apply_op_device(self.h, f, dagger, b, x.shape[0], _ptr(x), _ptr(y),
+                                         C.byref(bo), _stream(stream)))
+        return bo.value
+
+    def propagate_device(self, b, x, dtau, y, log_scale, steps=None, stream=None):
+        _log(f"propagate_device block={b} n_vec={x.shape[0]}")
+        _check(lib().hyb_propagate_device(self.h, b, x.shape[0], _ptr(x), _ptr(dtau), _ptr(y),
+                                          _ptr(log_scale), _ptr(steps), _stream(stream)))
+
+    def set_variant(self, v):
+        _check(lib().hyb_set_trace_variant(self.h, v))
+
+    def variant(self):
+        v = C.c_int32()
+        _check(lib().hyb_get_trace_variant(self.h, C.byref(v)))
+        return v.value
+
+    def set_timing(self, on=True):
+        _check(lib().hyb_set_timing(self.h, 1 if on else 0))
+
+    def last_timing(self):
+        ms = np.zeros(3, np.float32)
+        _check(lib().hyb_last_timing(self.h, _ptr(ms)))
+        return ms
+
+    def trace_batch(self, batch, beta=None, stream=None):
+        """Host batch (inputs.ConfigBatch) -> TraceResult (host)."""
+        beta = batch.beta if beta is None else beta
+        n = batch.n_configs
+        cfg = ConfigBatchC(n_configs=n, offsets=_ptr(batch.offsets), tau=_ptr(batch.tau),
+                           flavor=_ptr(batch.flavor), dagger=_ptr(batch.dagger), on_device=0)
+        res = TraceResult(np.zeros(n, np.int8), np.zeros(n), np.zeros(n, np.int32),
+                          np.zeros(n, np.int32), np.zeros(n, np.int32))
+        out = TraceOutC(log_abs=_ptr(res.log_abs), sign=_ptr(res.sign),
+                        krylov_steps=_ptr(res.krylov_steps), substeps=_ptr(res.substeps),
+                        feasible_paths=_ptr(res.feasible_paths), on_device=0)
+        _log(f"trace_batch n_configs={n} n_ops={len(batch.tau)} beta={beta} variant={self.variant()}")
+        _check(lib().hyb_trace_batch(self.h, C.byref(cfg), beta, C.byref(out), _stream(stream)))
+        _log("trace_batch done")
+        return res
+
+    def trace_batch_device(self, dev_batch, beta, out, stream=None):
+        """dev_batch / out: dicts of torch device tensors (see bench.py)."""
+        cfg = ConfigBatchC(n_configs=dev_batch["offsets"].numel() - 1, offsets=_ptr(dev_batch["offsets"]),
+                           tau=_ptr(dev_batch["tau"]), flavor=_ptr(dev_batch["flavor"]),
+                           dagger=_ptr(dev_batch["dagger"]), on_device=1)
+        o = TraceOutC(log_abs=_ptr(out["log_abs"]), sign=_ptr(out["sign"]),
+                      krylov_steps=_ptr(out.get("krylov_steps")), substeps=_ptr(out.get("substeps")),
+                      feasible_paths=_ptr(out.get("feasible_paths")), on_device=1)
+        _check(lib().hyb_trace_batch(self.h, C.byref(cfg), beta, C.byref(o), _stream(stream)))
+
+    def block_spmm(self, b, X, Y, n_vec, stream=None):
+        _check(lib().hyb_block_spmm(self.h, b, n_vec, _ptr(X), _ptr(Y), _stream(stream)))
+
+
+def variant_names():
+    n = C.c_int32()
+    _check(lib().hyb_trace_variant_count(C.byref(n)))
+    out = []
+    for i in range(n.value):
+        buf = C.create_string_buffer(64)
+        _check(lib().hyb_trace_variant_name(i, buf, 64))
+        out.append(buf.value.decode())
+    return out
+
+
+def model_for_workload(w, upload=True, **kw):
+    args = dict(precision=w.precision, retain_window=w.retain_window,
+                krylov_max=min(w.krylov_max, 12),
+                krylov_tol=(1e-13 if w.precision == "fp64" else 1e-7))
+    args.update(kw)
+    return Model(w.params, upload=upload, **args)

@@ -474,3 +474,17 @@ def test_propagation_matches_expm():
             ref = sla.expm(-dt * (Hb - o.spec.E0 * np.eye(len(Hb)))) @ v
             got = o.propagate(b, v, dt)
             assert np.linalg.norm(got - ref) <= 1e-12 * max(1.0, np.linalg.norm(ref))
+
+
+def test_log_scaled_propagation_matches_plain():
+    w = I.workload(1)
+    o = T.build(w.params, w.retain_window)
+    rng = np.random.default_rng(1)
+    for b in (12, 20, 25):
+        v = rng.standard_normal(len(o.spec.states[b]))
+        for dt in (0.05, 1.0, 4.0):
+            y, ls = o.propagate_log(b, v, dt)
+            ref = o.propagate(b, v, dt)
+            assert np.linalg.norm(np.exp(ls) * y - ref) <= 1e-13 * np.linalg.norm(ref)
+            assert abs(np.linalg.norm(y) - 1) < 1e-14
+
