@@ -10,10 +10,22 @@ with O_k = c^dag_{f_k} if dagger_k else c_{f_k}, 0 <= tau_1 < ... < tau_n < beta
 The value is the literal operator product in time order (latest operator
 leftmost); no time-ordering permutation sign is attached.
 
-Each imaginary-time evolution inside block b is written out as the matrix
-function V_b diag(exp(-dtau (E_b - E0))) V_b^T from the block's eigen-
-decomposition.  Because |E_i> is an eigenstate, the two edge intervals reduce
-to the scalar exp(-(beta - tau_n + tau_1) (E_i - E0)) (step 3).  Energies are
+Each imaginary-time evolution inside block b is the matrix exponential
+exp(-dtau (H_b - e_b)) (e_b the block's lowest eigenvalue) applied to the
+vector.  For blocks of up to EXPM_MAX_DIM states it is evaluated by scipy's
+scaling-and-squaring Pade expm; for larger blocks by the block's eigen-
+decomposition V_b diag(exp(-dtau (E_b - e_b))) V_b^T.  The two agree to
+rounding, but the eigenvector route mixes symmetry sectors inside (near-)
+degenerate eigenvalue clusters at the level eps*|H|/gap, and long intervals
+then amplify that mixing into components that are zero by symmetry; the
+polynomial route keeps the vector in its own symmetry sector (it is a power
+series in H).  Because |E_i> is an eigenstate, the two edge intervals reduce
+to the scalar exp(-(beta - tau_n + tau_1) (E_i - E0)) (step 3).
+
+An operator that leaves less than zero_tol of the (unit) vector's norm ends
+the path: in exact arithmetic such results are zeros imposed by symmetry
+(for instance c_f acting on a vector with no weight on occupied f inside the
+sector reached), and numerically they are rounding noise.  Energies are
 shifted by the ground energy E0 (and, inside a propagation, by the block's
 own lowest eigenvalue), and the vector is renormalised after every step with
 its log-norm kept aside; these are exact rescalings that keep the float64
@@ -23,6 +35,7 @@ from __future__ import annotations
 
 from dataclasses import dataclass
 import numpy as np
+import scipy.linalg as sla
 
 from .fock import FockOperators, block_key
 from .hamiltonian import BlockSpectrum, Retained
@@ -49,15 +62,21 @@ class TraceResult:
         return out
 
 
+EXPM_MAX_DIM = 400
+
+
 class TraceOracle:
     """Holds a block spectrum, a retained set and cached operator blocks."""
 
-    def __init__(self, spec: BlockSpectrum, retained: Retained, ops: FockOperators | None = None):
+    def __init__(self, spec: BlockSpectrum, retained: Retained, ops: FockOperators | None = None,
+                 zero_tol: float = 1e-10, method: str = "auto"):
         self.spec = spec
         self.R = retained
         self.n = spec.n_orb
         self.ops = ops or FockOperators(self.n)
         self._opblk = {}
+        self.zero_tol = zero_tol
+        self.method = method   # "auto" | "expm" | "eigh"
 
     # -- sector bookkeeping -------------------------------------------------
     def _nud(self, b):
@@ -95,9 +114,13 @@ class TraceOracle:
 
         The block's lowest eigenvalue is factored out before exponentiating so
         that long intervals in high-lying blocks do not underflow."""
-        Vb, Eb = self.spec.V[b], self.spec.E[b]
+        Vb, Eb, Hb = self.spec.V[b], self.spec.E[b], self.spec.H[b]
         emin = float(Eb.min())
-        y = Vb @ (np.exp(-dtau * (Eb - emin)) * (Vb.T @ v))
+        use_expm = self.method == "expm" or (self.method == "auto" and len(Eb) <= EXPM_MAX_DIM)
+        if use_expm:
+            y = sla.expm(-dtau * (Hb - emin * np.eye(len(Eb)))) @ v
+        else:
+            y = Vb @ (np.exp(-dtau * (Eb - emin)) * (Vb.T @ v))
         s = np.linalg.norm(y)
         return y / s, np.log(s) - dtau * (emin - self.spec.E0)
 
@@ -129,7 +152,7 @@ class TraceOracle:
             b, M = self.op_block(int(flavor[k]), int(dagger[k]), b)
             v = M @ v
             s = np.linalg.norm(v)
-            if s == 0.0:
+            if s <= self.zero_tol:
                 return True, 0, -np.inf
             ell += np.log(s)
             v = v / s
@@ -168,10 +191,11 @@ def signed_logsum(signs, logs):
     return (1 if s > 0 else -1), m + np.log(abs(s))
 
 
-def build(params, window: float, ops: FockOperators | None = None, hc_literal: bool = False):
+def build(params, window: float, ops: FockOperators | None = None, hc_literal: bool = False,
+          zero_tol: float = 1e-10, method: str = "auto"):
     """Convenience: spectrum + retained set + oracle for a parameter set."""
     from .hamiltonian import block_spectrum, retained_set
     ops = ops or FockOperators(params.n_orb)
     spec = block_spectrum(params, hc_literal=hc_literal, ops=ops)
     R = retained_set(spec, window)
-    return TraceOracle(spec, R, ops)
+    return TraceOracle(spec, R, ops, zero_tol=zero_tol, method=method)

@@ -32,12 +32,27 @@ __global__ void k_scan(TraceParams P) {
   if (id < int64_t(P.n_configs) * P.n_ret) scan_pair(P, id);
 }
 
+template <typename VT, int NT>
+__global__ __launch_bounds__(NT) void k_path_init(TraceParams P) {
+  path_init<VT, NT>(P, blockIdx.x);
+}
+
+template <typename VT, int NT, int RPT>
+__global__ __launch_bounds__(NT) void k_path_op(TraceParams P, int k) {
+  __shared__ double red[NT / 64];
+  path_op<VT, NT, RPT>(P, blockIdx.x, k, red);
+}
+
 template <typename VT, int NT, int RPT, int MAXM>
-__global__ __launch_bounds__(NT) void k_trace(TraceParams P) {
-  using E = PathEngine<VT, NT, RPT, MAXM>;
-  __shared__ typename E::Smem S;
-  E eng(P, S);
-  eng.run_queue();
+__global__ __launch_bounds__(NT) void k_path_prop(TraceParams P, int k) {
+  __shared__ typename PathEngine<VT, NT, RPT, MAXM>::Smem S;
+  path_prop<VT, NT, RPT, MAXM>(P, blockIdx.x, k, S);
+}
+
+template <typename VT, int NT, int RPT>
+__global__ __launch_bounds__(NT) void k_path_final(TraceParams P) {
+  __shared__ double red[NT / 64];
+  path_final<VT, NT, RPT>(P, blockIdx.x, red);
 }
 
 __global__ void k_reduce(TraceParams P, double* out_log, int8_t* out_sign, int32_t* out_steps,
@@ -110,12 +125,18 @@ struct Variant {
   const char* name;
   int fp64;   // 1: float64 vectors, 0: float32 (mixed)
   int nt, rpt, maxm;
-  const void* trace_fn;
-  const void* prop_fn;
+  const void* init_fn;   // k_path_init
+  const void* op_fn;     // k_path_op
+  const void* step_fn;   // k_path_prop
+  const void* final_fn;  // k_path_final
+  const void* prop_fn;   // k_propagate (parity hook)
 };
 
-#define VARIANT(VT, NT, RPT, MAXM, NAME)                                                     \
-  {NAME, sizeof(VT) == 8, NT, RPT, MAXM, reinterpret_cast<const void*>(&k_trace<VT, NT, RPT, MAXM>), \
+#define VARIANT(VT, NT, RPT, MAXM, NAME)                                                      \
+  {NAME, sizeof(VT) == 8, NT, RPT, MAXM, reinterpret_cast<const void*>(&k_path_init<VT, NT>),  \
+   reinterpret_cast<const void*>(&k_path_op<VT, NT, RPT>),                                    \
+   reinterpret_cast<const void*>(&k_path_prop<VT, NT, RPT, MAXM>),                            \
+   reinterpret_cast<const void*>(&k_path_final<VT, NT, RPT>),                                 \
    reinterpret_cast<const void*>(&k_propagate<VT, NT, RPT, MAXM>)}
 
 static const Variant kVariants[] = {
@@ -221,6 +242,7 @@ static TraceParams base_params(const hyb_model* m) {
   P.kmax = m->p.krylov_max;
   P.max_substeps = 32;
   P.work_budget = 200000;
+  P.zero_tol2 = (m->p.precision == HYB_FP64) ? 1e-20 : 1e-10;
   return P;
 }
 
@@ -375,6 +397,14 @@ int hyb_trace_batch(hyb_model* m, const hyb_config_batch* cfg, double beta, hyb_
     o_fl = take(std::max<int64_t>(n_ops, 1) * sizeof(int16_t));
     o_dg = take(std::max<int64_t>(n_ops, 1) * sizeof(int8_t));
   }
+  const size_t vbytes = V.fp64 ? sizeof(double) : sizeof(float);
+  const int vstride = (m->max_dim + 63) & ~63;
+  const size_t o_sblock = take(npairs * sizeof(int32_t));
+  const size_t o_sstatus = take(npairs * sizeof(int32_t));
+  const size_t o_ssteps = take(npairs * sizeof(int32_t));
+  const size_t o_ssubs = take(npairs * sizeof(int32_t));
+  const size_t o_sell = take(npairs * sizeof(double));
+  const size_t o_svec = take(2 * size_t(npairs) * vstride * vbytes);
   size_t o_olog = 0, o_osign = 0, o_osteps = 0, o_osub = 0, o_ofeas = 0;
   if (!out->on_device) {
     o_olog = take(nc * sizeof(double));
@@ -397,6 +427,13 @@ int hyb_trace_batch(hyb_model* m, const hyb_config_batch* cfg, double beta, hyb_
   P.p_log = reinterpret_cast<double*>(ws + o_plog);
   P.p_steps = reinterpret_cast<int32_t*>(ws + o_psteps);
   P.p_sub = reinterpret_cast<int32_t*>(ws + o_psub);
+  P.st_block = reinterpret_cast<int32_t*>(ws + o_sblock);
+  P.st_status = reinterpret_cast<int32_t*>(ws + o_sstatus);
+  P.st_steps = reinterpret_cast<int32_t*>(ws + o_ssteps);
+  P.st_subs = reinterpret_cast<int32_t*>(ws + o_ssubs);
+  P.st_ell = reinterpret_cast<double*>(ws + o_sell);
+  P.st_vec = ws + o_svec;
+  P.vstride = vstride;
   if (cfg->on_device) {
     P.offsets = cfg->offsets;
     P.tau = cfg->tau;
@@ -430,15 +467,25 @@ int hyb_trace_batch(hyb_model* m, const hyb_config_batch* cfg, double beta, hyb_
   if (m->timing) HIP_TRY(hipEventRecord(ev[0], s));
   const int scan_threads = 256;
   k_scan<<<unsigned((npairs + scan_threads - 1) / scan_threads), scan_threads, 0, s>>>(P);
+  HIP_TRY(hipGetLastError());
+  // queued paths, longest configuration and validation errors
+  int32_t cnt[3] = {0, 0, 0};
+  HIP_TRY(hipMemcpyAsync(cnt, P.counters, sizeof cnt, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (cnt[2]) return error_from_bits(cnt[2]);
+  const int nwork = cnt[0], max_ops = cnt[1];
+  if (nwork < 0 || nwork > npairs) return set_error(HYB_E_HIP, "corrupt path queue (%d)", nwork);
   if (m->timing) HIP_TRY(hipEventRecord(ev[1], s));
-  // persistent grid: as many workgroups as can be resident, capped by the pair count
-  int per_cu = 0;
-  HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, V.trace_fn, V.nt, 0));
-  int n_cu = 0;
-  HIP_TRY(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
-  const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(npairs, int64_t(std::max(per_cu, 1)) * n_cu));
-  void* args[] = {&P};
-  HIP_TRY(hipLaunchKernel(V.trace_fn, dim3(unsigned(grid)), dim3(V.nt), args, 0, s));
+  if (nwork > 0) {
+    void* a0[] = {&P};
+    HIP_TRY(hipLaunchKernel(V.init_fn, dim3(unsigned(nwork)), dim3(V.nt), a0, 0, s));
+    for (int k = 0; k < max_ops; ++k) {
+      void* ak[] = {&P, &k};
+      if (k > 0) HIP_TRY(hipLaunchKernel(V.step_fn, dim3(unsigned(nwork)), dim3(V.nt), ak, 0, s));
+      HIP_TRY(hipLaunchKernel(V.op_fn, dim3(unsigned(nwork)), dim3(V.nt), ak, 0, s));
+    }
+    HIP_TRY(hipLaunchKernel(V.final_fn, dim3(unsigned(nwork)), dim3(V.nt), a0, 0, s));
+  }
   if (m->timing) HIP_TRY(hipEventRecord(ev[2], s));
   k_reduce<<<(nc + 255) / 256, 256, 0, s>>>(P, d_log, d_sign, d_steps, d_sub, d_feas);
   if (m->timing) HIP_TRY(hipEventRecord(ev[3], s));

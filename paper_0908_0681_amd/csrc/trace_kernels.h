@@ -1,10 +1,13 @@
 // Device code of the Krylov trace (gfx950, wave64).
 //
-// One workgroup evaluates one (configuration, retained state) path at a time and
-// pulls the next path from a device work queue (persistent launch).  The path's
-// vector lives in registers, RPT rows per thread (row = tid + k*NT); the Lanczos
-// basis V_0..V_m lives in registers too.  LDS holds only the vector being
-// gathered (operator application, SpMV) and the reduction partials.
+// The trace is evaluated step-synchronously over all feasible (configuration,
+// retained state) paths of a batch: one launch applies operator k to every path
+// whose configuration has an operator k, one launch propagates every such path
+// over the next interval.  Between launches a path's state (block, log-scale,
+// unit vector) lives in HBM.  Inside a propagation one workgroup owns one path:
+// the vector lives in registers, RPT rows per thread (row = tid + k*NT), the
+// Lanczos basis V_0..V_m lives in registers too, and LDS holds the vector being
+// gathered by the SpMV, the reduction partials and the small tridiagonal problem.
 //
 // Steps (Sec. III): the retained eigenstate enters with the scalar phase of the
 // two edge intervals (step 3); each operator is a signed gather between blocks
@@ -48,7 +51,7 @@ struct TraceParams {
   double beta;
   // work queue and per-path results (path id = config * n_ret + r)
   int32_t* work;
-  int32_t* counters;  // [0] queued paths, [1] next ticket, [2] error bits
+  int32_t* counters;  // [0] queued paths, [1] longest configuration, [2] error bits
   int8_t* p_sign;
   double* p_log;
   int32_t* p_steps;
@@ -59,7 +62,18 @@ struct TraceParams {
   int32_t max_substeps;
   int32_t n_pairs;     // n_configs * n_ret
   int32_t work_budget; // QR sweeps allowed per path before it is abandoned
+  // step-synchronous path state, indexed by queue slot w < counters[0]
+  int32_t* st_block;   // current block of the path
+  int32_t* st_status;  // PATH_ACTIVE / PATH_EMPTY / PATH_ZERO / PATH_FAILED
+  int32_t* st_steps;   // Lanczos steps so far
+  int32_t* st_subs;    // extra substeps forced by the depth cap
+  double* st_ell;      // running log-scale
+  void* st_vec;        // two ping-pong vector buffers [2][n_pairs][vstride] of VT
+  int32_t vstride;     // elements per path vector (>= largest block)
+  double zero_tol2;    // an operator leaving less than this squared norm ends the path
 };
+
+enum : int32_t { PATH_ACTIVE = 0, PATH_EMPTY = 1, PATH_ZERO = 2, PATH_FAILED = 3 };
 
 // ---------------------------------------------------------------------------
 // wavefront reductions (DPP inside rows of 16 lanes, then readlane)
@@ -113,7 +127,6 @@ struct PathEngine {
     VT vec[NT * RPT];
     double red[2][NW][NRED];
     Small small[NW];
-    int ticket, nwork;
   };
 
   const TraceParams& P;
@@ -482,107 +495,8 @@ struct PathEngine {
     return true;
   }
 
-  // Evaluates path id = config * n_ret + r and stores sign / log / diagnostics.
-  __device__ void run_path(int id) {
-    const int c = id / P.n_ret, r = id - c * P.n_ret;
-    const int64_t o0 = P.offsets[c], o1 = P.offsets[c + 1];
-    const int nops = int(o1 - o0);
-    const double Ei = P.ret_energy[r];
-    int steps = 0, subs = 0;
-    work = 0;
-    nops_budget = nops;
-    if (nops == 0) {
-      if (tid == 0) {
-        P.p_sign[id] = 1;
-        P.p_log[id] = -P.beta * Ei;
-        P.p_steps[id] = 0;
-        P.p_sub[id] = 0;
-      }
-      return;
-    }
-    const double* tau = P.tau + o0;
-    double ell = -(P.beta - tau[nops - 1] + tau[0]) * (Ei - P.E0);
-    const VT* e_i = ret_vec() + P.ret_off[r];
-    VT x[RPT];
-    BlockDev B = P.blocks[P.ret_block[r]];
-#pragma unroll
-    for (int k = 0; k < RPT; ++k) x[k] = (row(k) < B.dim) ? e_i[row(k)] : VT(0);
-    bool ok = true, zero = false;
-    for (int k = 0; k < nops; ++k) {
-      if (k > 0) {
-        ok = propagate(B, tau[k] - tau[k - 1], x, ell, steps, subs);
-        if (!ok) break;
-      }
-      const int f = P.flavor[o0 + k];
-      const int dg = P.dagger[o0 + k] ? 1 : 0;
-      int nu = B.n_up, nd = B.n_dn;
-      if (f < P.n_orb) nu += dg ? 1 : -1; else nd += dg ? 1 : -1;
-      if (nu < 0 || nu > P.n_orb || nd < 0 || nd > P.n_orb) {  // excluded by the scan
-        ok = false;
-        break;
-      }
-      const BlockDev Bt = P.blocks[nd * (P.n_orb + 1) + nu];
-      const double n2 = apply_op(B, Bt, f, dg, x);
-      B = Bt;
-      if (!(n2 > 0.0)) {
-        if (n2 != 0.0) atomicOr(&P.counters[2], ERR_NONFINITE);
-        zero = true;
-        break;
-      }
-      if (!isfinite(n2)) {
-        atomicOr(&P.counters[2], ERR_NONFINITE);
-        ok = false;
-        break;
-      }
-      ell += 0.5 * log(n2);
-      const double inv = 1.0 / sqrt(n2);
-#pragma unroll
-      for (int q = 0; q < RPT; ++q) x[q] = static_cast<VT>(to_d(x[q]) * inv);
-    }
-    double ov = 0.0;
-    if (ok && !zero) {
-      double part = 0.0;
-#pragma unroll
-      for (int k = 0; k < RPT; ++k)
-        if (row(k) < B.dim) part += to_d(e_i[row(k)]) * to_d(x[k]);
-      ov = block_sum1(part);
-    }
-    if (tid == 0) {
-      if (!ok || zero || ov == 0.0) {
-        P.p_sign[id] = 0;
-        P.p_log[id] = -INFINITY;
-      } else {
-        P.p_sign[id] = ov > 0.0 ? 1 : -1;
-        P.p_log[id] = ell + log(fabs(ov)) - P.beta * P.E0;
-      }
-      P.p_steps[id] = steps;
-      P.p_sub[id] = subs;
-    }
-  }
-  // Persistent work loop: take tickets until the queue of feasible paths is empty.
-  // Tickets only grow, and no workgroup goes past n_pairs of them, so the loop
-  // ends for every workgroup whatever the queue holds.
-  __device__ void run_queue() {
-    for (;;) {
-      if (tid == 0) {
-        S.ticket = atomicAdd(&P.counters[1], 1);
-        S.nwork = __atomic_load_n(&P.counters[0], __ATOMIC_RELAXED);
-      }
-      __syncthreads();
-      const int t = S.ticket;
-      const int nwork = S.nwork;
-      __syncthreads();
-      if (t >= nwork || t >= P.n_pairs) break;
-      const int id = P.work[t];
-      if (id < 0 || id >= P.n_pairs) break;
-      run_path(id);
-    }
-  }
 };
 
-// Validates configurations and walks the (n_up, n_dn) sector path of every
-// (config, retained state) pair; queues the pairs whose path stays physical and
-// returns to its starting block (the others are structural zeros).
 __device__ inline void scan_pair(const TraceParams& P, int64_t id) {
   const int c = int(id / P.n_ret), r = int(id - int64_t(c) * P.n_ret);
   const int64_t o0 = P.offsets[c], o1 = P.offsets[c + 1];
@@ -613,6 +527,7 @@ __device__ inline void scan_pair(const TraceParams& P, int64_t id) {
   P.p_steps[id] = 0;
   P.p_sub[id] = feas ? 0 : -1;
   if (err && r == 0) atomicOr(&P.counters[2], err);
+  if (r == 0 && o1 > o0) atomicMax(&P.counters[1], int(o1 - o0));
   if (feas) {
     const int slot = atomicAdd(&P.counters[0], 1);
     P.work[slot] = int32_t(id);
@@ -652,6 +567,191 @@ __device__ inline void reduce_config(const TraceParams& P, int c, double* out_lo
   if (out_steps) out_steps[c] = steps;
   if (out_sub) out_sub[c] = subs;
   if (out_feas) out_feas[c] = feas;
+}
+
+// ---- step-synchronous path kernels (one workgroup per queued path) ----------
+
+template <typename VT>
+__device__ __forceinline__ VT* path_vec(const TraceParams& P, int parity, int w) {
+  return static_cast<VT*>(P.st_vec) + (int64_t(parity) * P.n_pairs + w) * P.vstride;
+}
+
+// Step 3: the retained eigenstate enters with the phase of the two edge intervals.
+template <typename VT, int NT>
+__device__ inline void path_init(const TraceParams& P, int w) {
+  const int id = P.work[w];
+  const int c = id / P.n_ret, r = id - c * P.n_ret;
+  const int64_t o0 = P.offsets[c], o1 = P.offsets[c + 1];
+  const int b = P.ret_block[r];
+  const int dim = P.blocks[b].dim;
+  const VT* src = (sizeof(VT) == 8) ? reinterpret_cast<const VT*>(P.ret_vec64 + P.ret_off[r])
+                                    : reinterpret_cast<const VT*>(P.ret_vec32 + P.ret_off[r]);
+  VT* dst = path_vec<VT>(P, 0, w);
+  for (int i = threadIdx.x; i < dim; i += NT) dst[i] = src[i];
+  if (threadIdx.x == 0) {
+    const double Ei = P.ret_energy[r];
+    P.st_block[w] = b;
+    P.st_status[w] = (o1 > o0) ? PATH_ACTIVE : PATH_EMPTY;
+    P.st_steps[w] = 0;
+    P.st_subs[w] = 0;
+    P.st_ell[w] = (o1 > o0) ? -(P.beta - P.tau[o1 - 1] + P.tau[o0]) * (Ei - P.E0) : 0.0;
+  }
+}
+
+// Step 4: operator k of the path's configuration, a signed gather from block b to
+// the target block, then renormalisation with the log of the norm kept in ell.
+template <typename VT, int NT, int RPT>
+__device__ inline void path_op(const TraceParams& P, int w, int k, double* red) {
+  if (P.st_status[w] != PATH_ACTIVE) return;
+  const int id = P.work[w];
+  const int c = id / P.n_ret;
+  const int64_t o0 = P.offsets[c], o1 = P.offsets[c + 1];
+  if (k >= o1 - o0) return;
+  const int f = P.flavor[o0 + k];
+  const int dg = P.dagger[o0 + k] ? 1 : 0;
+  const BlockDev B = P.blocks[P.st_block[w]];
+  int nu = B.n_up, nd = B.n_dn;
+  if (f < P.n_orb) nu += dg ? 1 : -1; else nd += dg ? 1 : -1;
+  if (nu < 0 || nu > P.n_orb || nd < 0 || nd > P.n_orb) {  // excluded by the scan
+    if (threadIdx.x == 0) P.st_status[w] = PATH_FAILED;
+    return;
+  }
+  const int bt = nd * (P.n_orb + 1) + nu;
+  const BlockDev Bt = P.blocks[bt];
+  const VT* src = path_vec<VT>(P, k & 1, w);
+  VT* dst = path_vec<VT>(P, (k + 1) & 1, w);
+  const uint32_t bit = 1u << f;
+  VT val[RPT];
+  double part = 0.0;
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) {
+    const int r = threadIdx.x + q * NT;
+    VT v = VT(0);
+    if (r < Bt.dim) {
+      const uint32_t t = P.states[Bt.state_off + r];
+      // source state s with O|s> ~ |t>: a creator needs bit f set in t, an annihilator unset
+      const bool has = dg ? ((t & bit) != 0u) : ((t & bit) == 0u);
+      if (has) {
+        const uint32_t s = t ^ bit;
+        const VT x = src[P.rank[s]];
+        v = (__popc(s & (bit - 1u)) & 1) ? -x : x;
+      }
+    }
+    val[q] = v;
+    part += to_d(v) * to_d(v);
+  }
+  part = wave_sum(part);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = part;
+  __syncthreads();
+  double n2 = 0.0;
+#pragma unroll
+  for (int q = 0; q < NT / 64; ++q) n2 += red[q];
+  // The input is a unit vector: a result this small is a zero imposed by symmetry
+  // in exact arithmetic and rounding noise in floating point.
+  if (!(n2 > P.zero_tol2) || !isfinite(n2)) {
+    if (threadIdx.x == 0) {
+      const bool zero = (n2 >= 0.0) && (n2 <= P.zero_tol2);
+      P.st_status[w] = zero ? PATH_ZERO : PATH_FAILED;
+      if (!zero) atomicOr(&P.counters[2], ERR_NONFINITE);
+    }
+    return;
+  }
+  const double inv = 1.0 / sqrt(n2);
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) {
+    const int r = threadIdx.x + q * NT;
+    if (r < Bt.dim) dst[r] = static_cast<VT>(to_d(val[q]) * inv);
+  }
+  if (threadIdx.x == 0) {
+    P.st_block[w] = bt;
+    P.st_ell[w] += 0.5 * log(n2);
+  }
+}
+
+// Step 5: Krylov propagation of the path's vector over tau_k - tau_{k-1}, in place.
+template <typename VT, int NT, int RPT, int MAXM>
+__device__ inline void path_prop(const TraceParams& P, int w, int k, typename PathEngine<VT, NT, RPT, MAXM>::Smem& S) {
+  using E = PathEngine<VT, NT, RPT, MAXM>;
+  if (P.st_status[w] != PATH_ACTIVE) return;
+  const int id = P.work[w];
+  const int c = id / P.n_ret;
+  const int64_t o0 = P.offsets[c], o1 = P.offsets[c + 1];
+  if (k >= o1 - o0) return;
+  E eng(P, S);
+  const BlockDev B = P.blocks[P.st_block[w]];
+  VT* vec = path_vec<VT>(P, k & 1, w);
+  VT x[RPT];
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) {
+    const int r = eng.row(q);
+    x[q] = (r < B.dim) ? vec[r] : VT(0);
+  }
+  double ell = 0.0;
+  int steps = 0, subs = 0;
+  eng.work = 0;
+  eng.nops_budget = 1;
+  const bool ok = eng.propagate(B, P.tau[o0 + k] - P.tau[o0 + k - 1], x, ell, steps, subs);
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) {
+    const int r = eng.row(q);
+    if (r < B.dim) vec[r] = x[q];
+  }
+  if (threadIdx.x == 0) {
+    P.st_ell[w] += ell;
+    P.st_steps[w] += steps;
+    P.st_subs[w] += subs;
+    if (!ok) P.st_status[w] = PATH_FAILED;
+  }
+}
+
+// Step 7: overlap with <E_i| closes the path; writes the per-path sign / log.
+template <typename VT, int NT, int RPT>
+__device__ inline void path_final(const TraceParams& P, int w, double* red) {
+  const int id = P.work[w];
+  const int c = id / P.n_ret, r = id - c * P.n_ret;
+  const int status = P.st_status[w];
+  const double Ei = P.ret_energy[r];
+  if (status == PATH_EMPTY) {
+    if (threadIdx.x == 0) {
+      P.p_sign[id] = 1;
+      P.p_log[id] = -P.beta * Ei;
+      P.p_steps[id] = 0;
+      P.p_sub[id] = 0;
+    }
+    return;
+  }
+  const int64_t nops = P.offsets[c + 1] - P.offsets[c];
+  const int b = P.ret_block[r];
+  const int dim = P.blocks[b].dim;
+  const VT* v = path_vec<VT>(P, int(nops & 1), w);
+  const VT* e = (sizeof(VT) == 8) ? reinterpret_cast<const VT*>(P.ret_vec64 + P.ret_off[r])
+                                  : reinterpret_cast<const VT*>(P.ret_vec32 + P.ret_off[r]);
+  double part = 0.0;
+  if (status == PATH_ACTIVE && P.st_block[w] == b) {
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int i = threadIdx.x + q * NT;
+      if (i < dim) part += to_d(e[i]) * to_d(v[i]);
+    }
+  }
+  part = wave_sum(part);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = part;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double ov = 0.0;
+#pragma unroll
+    for (int q = 0; q < NT / 64; ++q) ov += red[q];
+    if (status != PATH_ACTIVE || ov == 0.0) {
+      P.p_sign[id] = 0;
+      P.p_log[id] = -INFINITY;
+    } else {
+      P.p_sign[id] = ov > 0.0 ? 1 : -1;
+      P.p_log[id] = P.st_ell[w] + log(fabs(ov)) - P.beta * P.E0;
+    }
+    P.p_steps[id] = P.st_steps[w];
+    P.p_sub[id] = P.st_subs[w];
+    if (status == PATH_FAILED) atomicOr(&P.counters[2], ERR_NOCONV);
+  }
 }
 
 }  // namespace hyb

@@ -40,13 +40,10 @@ def compare(res, ref: T.TraceResult, tol, idx=None):
     for c in range(len(ref.sign)):
         so, lo = int(ref.sign[c]), float(ref.log_abs[c])
         sg, lg = int(res.sign[c]), float(res.log_abs[c])
-        if so == 0 and not np.any(ref.feasible[c]):
-            assert sg == 0 and lg == -math.inf, (c, sg, lg)
-            continue
         if so == 0:
-            # numerically cancelling sum: the GPU value must be tiny against sum|t_i|
-            big = np.max(ref.contrib_log[c])
-            assert sg == 0 or lg - big < math.log(tol) + 3, (c, lg, big)
+            # structural zeros (sector path) and symmetry zeros (an operator
+            # annihilating the vector) are exact on both sides
+            assert sg == 0 and lg == -math.inf, (c, sg, lg)
             continue
         if kap[c] <= 10:
             assert sg == so, (c, sg, so)
@@ -77,7 +74,8 @@ def w1():
 def w2():
     _require_gpu()
     w = I.workload(2)
-    return w, hyb.model_for_workload(w), T.build(w.params, w.retain_window)
+    # the mixed-precision kernel ends a path when an operator leaves < 1e-5 of the norm
+    return w, hyb.model_for_workload(w), T.build(w.params, w.retain_window, zero_tol=1e-5)
 
 
 def test_apply_op_device_bit_exact(w1):

@@ -488,3 +488,15 @@ def test_log_scaled_propagation_matches_plain():
             assert np.linalg.norm(np.exp(ls) * y - ref) <= 1e-13 * np.linalg.norm(ref)
             assert abs(np.linalg.norm(y) - 1) < 1e-14
 
+
+def test_polynomial_and_eigen_propagators_agree():
+    """The two exact propagators of the oracle (Pade expm and the block
+    eigendecomposition) agree on well-conditioned traces."""
+    w = I.workload(0)
+    b = w.batch(32)
+    r1 = T.build(w.params, -1.0, method="expm").trace_batch(b)
+    r2 = T.build(w.params, -1.0, method="eigh").trace_batch(b)
+    assert np.array_equal(r1.sign, r2.sign)
+    nz = r1.sign != 0
+    assert np.max(np.abs(r1.log_abs[nz] - r2.log_abs[nz])) < 1e-12
+
