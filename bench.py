@@ -1,0 +1,186 @@
+#!/usr/bin/env python3
+"""Trace-throughput benchmark of the Krylov CT-HYB local trace on one MI355X.
+
+A step is one hyb_trace_batch call over the whole synthetic batch of the
+5-orbital Kanamori workload (4096 configurations, beta = 50, per-flavor order
+~Poisson(5), FP64 Krylov with depth cap 12): sector scan, operator gathers,
+Krylov propagations, overlaps and the signed log-sum over the retained states.
+Inputs are resident in HBM before the timed region starts.
+
+Prints one JSON line with the throughput (trace evaluations / s), a roofline
+object for the dominant kernel (the Krylov propagation launches) and the CPU
+oracle timed on a bounded sample of the same workload on this host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Krylov trace evals/s (5,7 orb) & %HBM peak; eff. samples/s learned vs uniform"
+HBM_PEAK_GBS = 8000.0
+
+
+def device_batch(batch, torch):
+    return {
+        "offsets": torch.tensor(batch.offsets, device="cuda"),
+        "tau": torch.tensor(batch.tau, device="cuda"),
+        "flavor": torch.tensor(batch.flavor, device="cuda"),
+        "dagger": torch.tensor(batch.dagger, device="cuda"),
+    }
+
+
+def device_out(n, torch):
+    return {
+        "log_abs": torch.empty(n, dtype=torch.float64, device="cuda"),
+        "sign": torch.empty(n, dtype=torch.int8, device="cuda"),
+        "krylov_steps": torch.empty(n, dtype=torch.int32, device="cuda"),
+        "substeps": torch.empty(n, dtype=torch.int32, device="cuda"),
+        "feasible_paths": torch.empty(n, dtype=torch.int32, device="cuda"),
+        "rowsteps": torch.empty(n, dtype=torch.int64, device="cuda"),
+        "rows": torch.empty(n, dtype=torch.int64, device="cuda"),
+    }
+
+
+def measure_workload(k, steps, warmup, torch, hyb, I):
+    w = I.workload(k)
+    model = hyb.model_for_workload(w)
+    batch = w.batch()
+    dbatch = device_batch(batch, torch)
+    out = device_out(batch.n_configs, torch)
+    for _ in range(warmup):
+        model.trace_batch_device(dbatch, batch.beta, out)
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    start.record()
+    for _ in range(steps):
+        model.trace_batch_device(dbatch, batch.beta, out)
+    stop.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = start.elapsed_time(stop)
+    # one instrumented pass: per-launch events around the propagation kernels
+    model.set_timing(True)
+    model.trace_batch_device(dbatch, batch.beta, out)
+    torch.cuda.synchronize()
+    tm = model.last_timing()
+    model.set_timing(False)
+    vsize = 8 if w.precision == "fp64" else 4
+    rowsteps = int(out["rowsteps"].sum().item())
+    rows = int(out["rows"].sum().item())
+    steps_total = int(out["krylov_steps"].sum().item())
+    # algorithmic bytes of the propagation kernel: every Lanczos step reads and
+    # writes one block vector
+    prop_bytes = 2.0 * rowsteps * vsize
+    prop_ms, n_prop = float(tm[3]), int(tm[4])
+    op_ms, n_op = float(tm[5]), int(tm[6])
+    res = dict(
+        workload=w.name, n_configs=batch.n_configs, n_orb=w.params.n_orb, beta=w.beta,
+        precision=w.precision, ms_per_step=ms / steps, wall_s=wall,
+        traces_per_s=batch.n_configs * steps / (ms / 1e3),
+        prop_launches=n_prop, prop_ms=prop_ms, op_launches=n_op, op_ms=op_ms,
+        scan_ms=float(tm[0]), steps_ms=float(tm[1]), reduce_ms=float(tm[2]),
+        prop_bytes=prop_bytes, rowsteps=rowsteps, rows=rows, lanczos_steps=steps_total,
+        feasible_paths=int(out["feasible_paths"].sum().item()),
+        path_bytes=(2.0 * rowsteps + 2.0 * rows) * vsize,
+    )
+    res["mean_krylov_depth"] = steps_total / max(1, sum_intervals(batch, out, torch))
+    return res
+
+
+def sum_intervals(batch, out, torch):
+    """Intervals propagated = feasible paths x (ops - 1) summed over configurations."""
+    import numpy as np
+    nops = np.diff(batch.offsets)
+    feas = out["feasible_paths"].cpu().numpy()
+    return int(np.sum(feas * np.maximum(nops - 1, 0)))
+
+
+def cpu_baseline(k, n_sample):
+    """The FP64 oracle as it stands, on the first n_sample configurations."""
+    import numpy as np
+    from paper_0908_0681_amd import inputs as I
+    from oracle import trace as T
+    w = I.workload(k)
+    t0 = time.perf_counter()
+    o = T.build(w.params, w.retain_window)
+    setup = time.perf_counter() - t0
+    b = w.batch(n_sample)
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    t0 = time.perf_counter()
+    o.trace_batch(b)
+    dt = time.perf_counter() - t0
+    return {"value": n_sample / dt, "unit": "traces/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"first {n_sample} of the {w.n_configs} configurations of {w.name} "
+                      f"({dt:.1f} s; model setup {setup:.1f} s not counted)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--cpu-sample", type=int, default=192)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--seven", action="store_true", help="also time the 7-orbital mixed workload")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {a.gpus}): the trace batches shard "
+              f"by configuration without communication; run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_0908_0681_amd import inputs as I
+    from paper_0908_0681_amd import hyb
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    r5 = measure_workload(1, a.steps, a.warmup, torch, hyb, I)
+    achieved = r5["prop_bytes"] / (r5["prop_ms"] / 1e3) / 1e9 if r5["prop_ms"] > 0 else 0.0
+    line = {
+        "metric": METRIC,
+        "value": r5["traces_per_s"],
+        "unit": "traces/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": r5["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": r5["workload"], "n_configs": r5["n_configs"], "n_orb": 5,
+                   "beta": r5["beta"], "krylov_max": 12, "krylov_tol": 1e-13},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_path_prop (Krylov propagation launches)",
+                     "bytes_per_launch": r5["prop_bytes"] / max(r5["prop_launches"], 1),
+                     "ms_per_launch": r5["prop_ms"] / max(r5["prop_launches"], 1)},
+        "detail": {k: r5[k] for k in ("prop_launches", "prop_ms", "op_launches", "op_ms", "scan_ms",
+                                      "steps_ms", "reduce_ms", "lanczos_steps", "mean_krylov_depth",
+                                      "feasible_paths", "path_bytes")},
+    }
+    if a.seven:
+        r7 = measure_workload(2, max(2, a.steps // 5), 1, torch, hyb, I)
+        line["detail"]["kanamori-7orb-b40"] = {k: r7[k] for k in (
+            "traces_per_s", "ms_per_step", "prop_ms", "prop_launches", "prop_bytes", "mean_krylov_depth",
+            "feasible_paths")}
+    if not a.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(1, a.cpu_sample)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -165,6 +165,9 @@ typedef struct {
   int32_t* krylov_steps;  /* optional [n_configs]: Lanczos steps summed over the config's paths */
   int32_t* substeps;      /* optional [n_configs]: extra substeps forced by the depth cap */
   int32_t* feasible_paths;/* optional [n_configs]: retained states whose sector path stays physical */
+  int64_t* rowsteps;      /* optional [n_configs]: sum over paths and intervals of (Lanczos steps x
+                             block dimension), the vector traffic of the propagation */
+  int64_t* rows;          /* optional [n_configs]: sum over paths and intervals of the block dimension */
   int32_t on_device;      /* 1: outputs are device pointers (no host sync), 0: host */
 } hyb_trace_out;
 
@@ -188,11 +191,14 @@ int hyb_get_trace_variant(const hyb_model* m, int32_t* variant);
 int hyb_trace_variant_count(int32_t* n);
 int hyb_trace_variant_name(int32_t variant, char* buf, size_t len);
 
-/* Device time of the last hyb_trace_batch, split by kernel (HIP events on the
- * call's stream): ms[0] = scan, ms[1] = trace kernel, ms[2] = reduce.  Requires
- * hyb_set_timing(m, 1) before the call. */
+/* Device time of the last hyb_trace_batch (HIP events on the call's stream):
+ * out[0] = scan, out[1] = all path-step launches, out[2] = reduce (ms),
+ * out[3] = summed duration of the Krylov propagation launches (ms),
+ * out[4] = number of propagation launches, out[5] = summed duration of the
+ * operator launches (ms), out[6] = number of operator launches.
+ * Requires hyb_set_timing(m, 1) before the call. */
 int hyb_set_timing(hyb_model* m, int32_t on);
-int hyb_last_timing(const hyb_model* m, float* ms3);
+int hyb_last_timing(const hyb_model* m, float* out7);
 
 /* ---- block SpMM over many vectors ------------------------------------------ */
 

@@ -23,7 +23,7 @@ series in H).  Because |E_i> is an eigenstate, the two edge intervals reduce
 to the scalar exp(-(beta - tau_n + tau_1) (E_i - E0)) (step 3).
 
 An operator that leaves less than zero_tol of the (unit) vector's norm ends
-the path: in exact arithmetic such results are zeros imposed by symmetry
+the path, and so does a closing overlap <E_i|v> below zero_tol: in exact arithmetic such results are zeros imposed by symmetry
 (for instance c_f acting on a vector with no weight on occupied f inside the
 sector reached), and numerically they are rounding noise.  Energies are
 shifted by the ground energy E0 (and, inside a propagation, by the block's
@@ -157,7 +157,7 @@ class TraceOracle:
             ell += np.log(s)
             v = v / s
         ov = float(ei @ v)
-        if ov == 0.0:
+        if abs(ov) <= self.zero_tol:      # unit vectors: a symmetry zero in exact arithmetic
             return True, 0, -np.inf
         return True, (1 if ov > 0 else -1), ell + np.log(abs(ov)) - beta * E0
 

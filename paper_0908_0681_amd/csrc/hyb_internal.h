@@ -71,8 +71,9 @@ struct hyb_model {
   hyb::DeviceModel dev;
   int variant = -1;         // trace kernel variant (-1 = automatic)
   bool timing = false;
-  float last_ms[3] = {0, 0, 0};
+  float last_ms[7] = {0, 0, 0, 0, 0, 0, 0};
   void* events[4] = {nullptr, nullptr, nullptr, nullptr};
+  std::vector<void*> step_events;  // pairs around each step launch when timing
 };
 
 namespace hyb {

@@ -56,9 +56,10 @@ __global__ __launch_bounds__(NT) void k_path_final(TraceParams P) {
 }
 
 __global__ void k_reduce(TraceParams P, double* out_log, int8_t* out_sign, int32_t* out_steps,
-                         int32_t* out_sub, int32_t* out_feas) {
+                         int32_t* out_sub, int32_t* out_feas, int64_t* out_rowsteps, int64_t* out_rows) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c < P.n_configs) reduce_config(P, c, out_log, out_sign, out_steps, out_sub, out_feas);
+  if (c < P.n_configs)
+    reduce_config(P, c, out_log, out_sign, out_steps, out_sub, out_feas, out_rowsteps, out_rows);
 }
 
 // Operator application on a batch of vectors (parity hook).
@@ -199,6 +200,8 @@ void free_device(hyb_model* m) {
       (void)hipEventDestroy(reinterpret_cast<hipEvent_t>(e));
       e = nullptr;
     }
+  for (void* e : m->step_events) (void)hipEventDestroy(reinterpret_cast<hipEvent_t>(e));
+  m->step_events.clear();
   d = DeviceModel{};
   m->uploaded = false;
 }
@@ -390,6 +393,10 @@ int hyb_trace_batch(hyb_model* m, const hyb_config_batch* cfg, double beta, hyb_
   const size_t o_plog = take(npairs * sizeof(double));
   const size_t o_psteps = take(npairs * sizeof(int32_t));
   const size_t o_psub = take(npairs * sizeof(int32_t));
+  const size_t o_prs = take(npairs * sizeof(int64_t));
+  const size_t o_prw = take(npairs * sizeof(int64_t));
+  const size_t o_srs = take(npairs * sizeof(int64_t));
+  const size_t o_srw = take(npairs * sizeof(int64_t));
   size_t o_offs = 0, o_tau = 0, o_fl = 0, o_dg = 0;
   if (!cfg->on_device) {
     o_offs = take((nc + 1) * sizeof(int64_t));
@@ -405,13 +412,15 @@ int hyb_trace_batch(hyb_model* m, const hyb_config_batch* cfg, double beta, hyb_
   const size_t o_ssubs = take(npairs * sizeof(int32_t));
   const size_t o_sell = take(npairs * sizeof(double));
   const size_t o_svec = take(2 * size_t(npairs) * vstride * vbytes);
-  size_t o_olog = 0, o_osign = 0, o_osteps = 0, o_osub = 0, o_ofeas = 0;
+  size_t o_olog = 0, o_osign = 0, o_osteps = 0, o_osub = 0, o_ofeas = 0, o_ors = 0, o_orw = 0;
   if (!out->on_device) {
     o_olog = take(nc * sizeof(double));
     o_osign = take(nc * sizeof(int8_t));
     o_osteps = take(nc * sizeof(int32_t));
     o_osub = take(nc * sizeof(int32_t));
     o_ofeas = take(nc * sizeof(int32_t));
+    o_ors = take(nc * sizeof(int64_t));
+    o_orw = take(nc * sizeof(int64_t));
   }
   int rc = ensure_ws(m, off);
   if (rc) return rc;
@@ -432,6 +441,10 @@ int hyb_trace_batch(hyb_model* m, const hyb_config_batch* cfg, double beta, hyb_
   P.st_steps = reinterpret_cast<int32_t*>(ws + o_ssteps);
   P.st_subs = reinterpret_cast<int32_t*>(ws + o_ssubs);
   P.st_ell = reinterpret_cast<double*>(ws + o_sell);
+  P.st_rowsteps = reinterpret_cast<int64_t*>(ws + o_srs);
+  P.st_rows = reinterpret_cast<int64_t*>(ws + o_srw);
+  P.p_rowsteps = reinterpret_cast<int64_t*>(ws + o_prs);
+  P.p_rows = reinterpret_cast<int64_t*>(ws + o_prw);
   P.st_vec = ws + o_svec;
   P.vstride = vstride;
   if (cfg->on_device) {
@@ -460,6 +473,8 @@ int hyb_trace_batch(hyb_model* m, const hyb_config_batch* cfg, double beta, hyb_
   int32_t* d_steps = out->on_device ? out->krylov_steps : reinterpret_cast<int32_t*>(ws + o_osteps);
   int32_t* d_sub = out->on_device ? out->substeps : reinterpret_cast<int32_t*>(ws + o_osub);
   int32_t* d_feas = out->on_device ? out->feasible_paths : reinterpret_cast<int32_t*>(ws + o_ofeas);
+  int64_t* d_rs = out->on_device ? out->rowsteps : reinterpret_cast<int64_t*>(ws + o_ors);
+  int64_t* d_rw = out->on_device ? out->rows : reinterpret_cast<int64_t*>(ws + o_orw);
 
   hipEvent_t ev[4];
   for (int i = 0; i < 4; ++i) ev[i] = reinterpret_cast<hipEvent_t>(m->events[i]);
@@ -479,15 +494,28 @@ int hyb_trace_batch(hyb_model* m, const hyb_config_batch* cfg, double beta, hyb_
   if (nwork > 0) {
     void* a0[] = {&P};
     HIP_TRY(hipLaunchKernel(V.init_fn, dim3(unsigned(nwork)), dim3(V.nt), a0, 0, s));
+    const size_t need_ev = m->timing ? size_t(4) * max_ops : 0;
+    while (m->step_events.size() < need_ev) {
+      hipEvent_t e;
+      HIP_TRY(hipEventCreate(&e));
+      m->step_events.push_back(e);
+    }
+    auto ev_at = [&](size_t i) { return reinterpret_cast<hipEvent_t>(m->step_events[i]); };
     for (int k = 0; k < max_ops; ++k) {
       void* ak[] = {&P, &k};
-      if (k > 0) HIP_TRY(hipLaunchKernel(V.step_fn, dim3(unsigned(nwork)), dim3(V.nt), ak, 0, s));
+      if (k > 0) {
+        if (m->timing) HIP_TRY(hipEventRecord(ev_at(4 * k), s));
+        HIP_TRY(hipLaunchKernel(V.step_fn, dim3(unsigned(nwork)), dim3(V.nt), ak, 0, s));
+        if (m->timing) HIP_TRY(hipEventRecord(ev_at(4 * k + 1), s));
+      }
+      if (m->timing) HIP_TRY(hipEventRecord(ev_at(4 * k + 2), s));
       HIP_TRY(hipLaunchKernel(V.op_fn, dim3(unsigned(nwork)), dim3(V.nt), ak, 0, s));
+      if (m->timing) HIP_TRY(hipEventRecord(ev_at(4 * k + 3), s));
     }
     HIP_TRY(hipLaunchKernel(V.final_fn, dim3(unsigned(nwork)), dim3(V.nt), a0, 0, s));
   }
   if (m->timing) HIP_TRY(hipEventRecord(ev[2], s));
-  k_reduce<<<(nc + 255) / 256, 256, 0, s>>>(P, d_log, d_sign, d_steps, d_sub, d_feas);
+  k_reduce<<<(nc + 255) / 256, 256, 0, s>>>(P, d_log, d_sign, d_steps, d_sub, d_feas, d_rs, d_rw);
   if (m->timing) HIP_TRY(hipEventRecord(ev[3], s));
   HIP_TRY(hipGetLastError());
   int32_t flags = 0;
@@ -500,12 +528,34 @@ int hyb_trace_batch(hyb_model* m, const hyb_config_batch* cfg, double beta, hyb_
     if (out->substeps) HIP_TRY(hipMemcpyAsync(out->substeps, d_sub, nc * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     if (out->feasible_paths)
       HIP_TRY(hipMemcpyAsync(out->feasible_paths, d_feas, nc * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    if (out->rowsteps) HIP_TRY(hipMemcpyAsync(out->rowsteps, d_rs, nc * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    if (out->rows) HIP_TRY(hipMemcpyAsync(out->rows, d_rw, nc * sizeof(int64_t), hipMemcpyDeviceToHost, s));
   }
   HIP_TRY(hipStreamSynchronize(s));
   if (m->timing) {
     HIP_TRY(hipEventElapsedTime(&m->last_ms[0], ev[0], ev[1]));
     HIP_TRY(hipEventElapsedTime(&m->last_ms[1], ev[1], ev[2]));
     HIP_TRY(hipEventElapsedTime(&m->last_ms[2], ev[2], ev[3]));
+    float prop = 0.f, op = 0.f;
+    int nprop = 0, nop = 0;
+    if (nwork > 0)
+      for (int k = 0; k < max_ops; ++k) {
+        float t = 0.f;
+        if (k > 0) {
+          HIP_TRY(hipEventElapsedTime(&t, reinterpret_cast<hipEvent_t>(m->step_events[4 * k]),
+                                      reinterpret_cast<hipEvent_t>(m->step_events[4 * k + 1])));
+          prop += t;
+          ++nprop;
+        }
+        HIP_TRY(hipEventElapsedTime(&t, reinterpret_cast<hipEvent_t>(m->step_events[4 * k + 2]),
+                                    reinterpret_cast<hipEvent_t>(m->step_events[4 * k + 3])));
+        op += t;
+        ++nop;
+      }
+    m->last_ms[3] = prop;
+    m->last_ms[4] = float(nprop);
+    m->last_ms[5] = op;
+    m->last_ms[6] = float(nop);
   }
   return error_from_bits(flags);
 }

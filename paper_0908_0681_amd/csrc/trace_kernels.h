@@ -68,6 +68,10 @@ struct TraceParams {
   int32_t* st_steps;   // Lanczos steps so far
   int32_t* st_subs;    // extra substeps forced by the depth cap
   double* st_ell;      // running log-scale
+  int64_t* st_rowsteps;  // sum of Lanczos steps x block dimension
+  int64_t* st_rows;      // sum of block dimensions over intervals
+  int64_t* p_rowsteps;   // per (config, retained state) pair
+  int64_t* p_rows;
   void* st_vec;        // two ping-pong vector buffers [2][n_pairs][vstride] of VT
   int32_t vstride;     // elements per path vector (>= largest block)
   double zero_tol2;    // an operator leaving less than this squared norm ends the path
@@ -249,6 +253,55 @@ struct PathEngine {
   // another writes it.  Lane r (< m) keeps row r of the eigenvector matrix in W.q.
   // On return the eigenvalues are in W.a[W.cur][0..m).  Returns the sweep count.
   __device__ int small_eig(Small& W, int m) {
+    if (m <= 2) {
+      // closed forms: no sweep needed for the first two Lanczos steps
+      double l0, l1, q00 = 1.0, q01 = 0.0, q10 = 0.0, q11 = 1.0;
+      if (m == 1) {
+        l0 = W.alpha[0];
+        l1 = 0.0;
+      } else {
+        const double a = W.alpha[0], c = W.alpha[1], b = W.beta[0];
+        const double t = 0.5 * (a + c), d = 0.5 * (a - c), r = hypot(d, b);
+        l0 = t - r;
+        l1 = t + r;
+        if (b != 0.0) {
+          // eigenvector of l0 from the row without cancellation
+          double x0, x1;
+          if (d >= 0.0) {
+            x0 = b;
+            x1 = -d - r;
+          } else {
+            x0 = r - d;
+            x1 = -b;
+          }
+          const double nx = hypot(x0, x1);
+          x0 /= nx;
+          x1 /= nx;
+          q00 = x0;
+          q10 = x1;   // column 0 = eigenvector of l0
+          q01 = -x1;
+          q11 = x0;   // column 1 = eigenvector of l1
+        } else if (a > c) {
+          l0 = c;
+          l1 = a;
+          q00 = 0.0;
+          q10 = 1.0;
+          q01 = 1.0;
+          q11 = 0.0;
+        }
+      }
+      if (lane == 0) {
+        W.a[0][0] = l0;
+        W.a[0][1] = l1;
+        W.q[0] = q00;
+        W.q[1] = q01;
+        W.q[QLD] = q10;
+        W.q[QLD + 1] = q11;
+        W.cur = 0;
+      }
+      wave_sync();
+      return 0;
+    }
     if (lane < m) {
       W.a[0][lane] = W.alpha[lane];
       W.b[0][lane] = (lane + 1 < m) ? W.beta[lane] : 0.0;
@@ -526,6 +579,8 @@ __device__ inline void scan_pair(const TraceParams& P, int64_t id) {
   P.p_log[id] = -INFINITY;
   P.p_steps[id] = 0;
   P.p_sub[id] = feas ? 0 : -1;
+  P.p_rowsteps[id] = 0;
+  P.p_rows[id] = 0;
   if (err && r == 0) atomicOr(&P.counters[2], err);
   if (r == 0 && o1 > o0) atomicMax(&P.counters[1], int(o1 - o0));
   if (feas) {
@@ -537,13 +592,17 @@ __device__ inline void scan_pair(const TraceParams& P, int64_t id) {
 // Signed log-sum over the retained states of every configuration (step 8),
 // in a fixed order so that repeated runs are bitwise identical.
 __device__ inline void reduce_config(const TraceParams& P, int c, double* out_log, int8_t* out_sign,
-                                     int32_t* out_steps, int32_t* out_sub, int32_t* out_feas) {
+                                     int32_t* out_steps, int32_t* out_sub, int32_t* out_feas,
+                                     int64_t* out_rowsteps, int64_t* out_rows) {
   const int64_t base = int64_t(c) * P.n_ret;
   double mx = -INFINITY;
   int steps = 0, subs = 0, feas = 0;
+  int64_t rs = 0, rw = 0;
   for (int r = 0; r < P.n_ret; ++r) {
     if (P.p_sign[base + r] != 0) mx = fmax(mx, P.p_log[base + r]);
     steps += P.p_steps[base + r];
+    rs += P.p_rowsteps[base + r];
+    rw += P.p_rows[base + r];
     if (P.p_sub[base + r] >= 0) {
       ++feas;
       subs += P.p_sub[base + r];
@@ -567,6 +626,8 @@ __device__ inline void reduce_config(const TraceParams& P, int c, double* out_lo
   if (out_steps) out_steps[c] = steps;
   if (out_sub) out_sub[c] = subs;
   if (out_feas) out_feas[c] = feas;
+  if (out_rowsteps) out_rowsteps[c] = rs;
+  if (out_rows) out_rows[c] = rw;
 }
 
 // ---- step-synchronous path kernels (one workgroup per queued path) ----------
@@ -594,6 +655,8 @@ __device__ inline void path_init(const TraceParams& P, int w) {
     P.st_status[w] = (o1 > o0) ? PATH_ACTIVE : PATH_EMPTY;
     P.st_steps[w] = 0;
     P.st_subs[w] = 0;
+    P.st_rowsteps[w] = 0;
+    P.st_rows[w] = 0;
     P.st_ell[w] = (o1 > o0) ? -(P.beta - P.tau[o1 - 1] + P.tau[o0]) * (Ei - P.E0) : 0.0;
   }
 }
@@ -700,6 +763,8 @@ __device__ inline void path_prop(const TraceParams& P, int w, int k, typename Pa
     P.st_ell[w] += ell;
     P.st_steps[w] += steps;
     P.st_subs[w] += subs;
+    P.st_rowsteps[w] += int64_t(steps) * B.dim;
+    P.st_rows[w] += B.dim;
     if (!ok) P.st_status[w] = PATH_FAILED;
   }
 }
@@ -717,6 +782,8 @@ __device__ inline void path_final(const TraceParams& P, int w, double* red) {
       P.p_log[id] = -P.beta * Ei;
       P.p_steps[id] = 0;
       P.p_sub[id] = 0;
+      P.p_rowsteps[id] = 0;
+      P.p_rows[id] = 0;
     }
     return;
   }
@@ -741,7 +808,8 @@ __device__ inline void path_final(const TraceParams& P, int w, double* red) {
     double ov = 0.0;
 #pragma unroll
     for (int q = 0; q < NT / 64; ++q) ov += red[q];
-    if (status != PATH_ACTIVE || ov == 0.0) {
+    // unit vectors: an overlap below the zero threshold is a symmetry zero
+    if (status != PATH_ACTIVE || !(fabs(ov) * fabs(ov) > P.zero_tol2)) {
       P.p_sign[id] = 0;
       P.p_log[id] = -INFINITY;
     } else {
@@ -750,6 +818,8 @@ __device__ inline void path_final(const TraceParams& P, int w, double* red) {
     }
     P.p_steps[id] = P.st_steps[w];
     P.p_sub[id] = P.st_subs[w];
+    P.p_rowsteps[id] = P.st_rowsteps[w];
+    P.p_rows[id] = P.st_rows[w];
     if (status == PATH_FAILED) atomicOr(&P.counters[2], ERR_NOCONV);
   }
 }

@@ -48,7 +48,8 @@ class ConfigBatchC(C.Structure):
 
 class TraceOutC(C.Structure):
     _fields_ = [("log_abs", C.c_void_p), ("sign", C.c_void_p), ("krylov_steps", C.c_void_p),
-                ("substeps", C.c_void_p), ("feasible_paths", C.c_void_p), ("on_device", C.c_int32)]
+                ("substeps", C.c_void_p), ("feasible_paths", C.c_void_p), ("rowsteps", C.c_void_p),
+                ("rows", C.c_void_p), ("on_device", C.c_int32)]
 
 
 # name -> (restype, argtypes)
@@ -142,6 +143,8 @@ class TraceResult:
     krylov_steps: np.ndarray
     substeps: np.ndarray
     feasible_paths: np.ndarray
+    rowsteps: np.ndarray = None
+    rows: np.ndarray = None
 
 
 class Model:
@@ -255,7 +258,7 @@ class Model:
         _check(lib().hyb_set_timing(self.h, 1 if on else 0))
 
     def last_timing(self):
-        ms = np.zeros(3, np.float32)
+        ms = np.zeros(7, np.float32)
         _check(lib().hyb_last_timing(self.h, _ptr(ms)))
         return ms
 
@@ -266,10 +269,12 @@ class Model:
         cfg = ConfigBatchC(n_configs=n, offsets=_ptr(batch.offsets), tau=_ptr(batch.tau),
                            flavor=_ptr(batch.flavor), dagger=_ptr(batch.dagger), on_device=0)
         res = TraceResult(np.zeros(n, np.int8), np.zeros(n), np.zeros(n, np.int32),
-                          np.zeros(n, np.int32), np.zeros(n, np.int32))
+                          np.zeros(n, np.int32), np.zeros(n, np.int32), np.zeros(n, np.int64),
+                          np.zeros(n, np.int64))
         out = TraceOutC(log_abs=_ptr(res.log_abs), sign=_ptr(res.sign),
                         krylov_steps=_ptr(res.krylov_steps), substeps=_ptr(res.substeps),
-                        feasible_paths=_ptr(res.feasible_paths), on_device=0)
+                        feasible_paths=_ptr(res.feasible_paths), rowsteps=_ptr(res.rowsteps),
+                        rows=_ptr(res.rows), on_device=0)
         _log(f"trace_batch n_configs={n} n_ops={len(batch.tau)} beta={beta} variant={self.variant()}")
         _check(lib().hyb_trace_batch(self.h, C.byref(cfg), beta, C.byref(out), _stream(stream)))
         _log("trace_batch done")
@@ -282,7 +287,8 @@ class Model:
                            dagger=_ptr(dev_batch["dagger"]), on_device=1)
         o = TraceOutC(log_abs=_ptr(out["log_abs"]), sign=_ptr(out["sign"]),
                       krylov_steps=_ptr(out.get("krylov_steps")), substeps=_ptr(out.get("substeps")),
-                      feasible_paths=_ptr(out.get("feasible_paths")), on_device=1)
+                      feasible_paths=_ptr(out.get("feasible_paths")), rowsteps=_ptr(out.get("rowsteps")),
+                      rows=_ptr(out.get("rows")), on_device=1)
         _check(lib().hyb_trace_batch(self.h, C.byref(cfg), beta, C.byref(o), _stream(stream)))
 
     def block_spmm(self, b, X, Y, n_vec, stream=None):
@@ -300,9 +306,22 @@ def variant_names():
     return out
 
 
-def model_for_workload(w, upload=True, **kw):
+def model_for_workload(w, upload=True, use_cache=True, **kw):
+    """Model of a benchmark workload; applies the autotuned kernel variant if cached."""
     args = dict(precision=w.precision, retain_window=w.retain_window,
                 krylov_max=min(w.krylov_max, 12),
                 krylov_tol=(1e-13 if w.precision == "fp64" else 1e-7))
     args.update(kw)
-    return Model(w.params, upload=upload, **args)
+    m = Model(w.params, upload=upload, **args)
+    if upload and use_cache:
+        try:
+            import torch
+            from . import autotune
+            key = autotune.cache_key(autotune.gpu_arch(), w.params.n_orb, m.precision)
+            name = autotune.load_cache().get(key, {}).get("variant")
+            if name in variant_names():
+                m.set_variant(variant_names().index(name))
+                _log(f"autotuned variant {name} for {key}")
+        except HybError:
+            pass
+    return m
