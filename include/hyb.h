@@ -191,9 +191,17 @@ int hyb_get_trace_variant(const hyb_model* m, int32_t* variant);
 int hyb_trace_variant_count(int32_t* n);
 int hyb_trace_variant_name(int32_t variant, char* buf, size_t len);
 
+/* Operators processed per launch of the path kernels: 1 launches one propagation
+ * and one operator kernel per operator index; c > 1 launches one kernel that takes
+ * every path through c operators (propagation + operator each); 0 = all operators
+ * in one launch.  Results are identical; only the schedule changes. */
+int hyb_set_chunk(hyb_model* m, int32_t chunk);
+int hyb_get_chunk(const hyb_model* m, int32_t* chunk);
+
 /* Device time of the last hyb_trace_batch (HIP events on the call's stream):
  * out[0] = scan, out[1] = all path-step launches, out[2] = reduce (ms),
- * out[3] = summed duration of the Krylov propagation launches (ms),
+ * out[3] = summed duration of the Krylov propagation launches (ms; with chunk > 1
+ * the chunk launches, propagation and operators together),
  * out[4] = number of propagation launches, out[5] = summed duration of the
  * operator launches (ms), out[6] = number of operator launches.
  * Requires hyb_set_timing(m, 1) before the call. */

@@ -49,6 +49,12 @@ class TraceResult:
     contrib_log: np.ndarray   # float64 [n_configs, n_retained]: log|t_i| incl. -beta*E0
     feasible: np.ndarray      # bool [n_configs, n_retained]: sector path stays physical
 
+    def rows(self, idx):
+        """The results of the configurations idx (a list), in that order."""
+        idx = list(idx)
+        return TraceResult(self.sign[idx], self.log_abs[idx], self.contrib_sign[idx],
+                           self.contrib_log[idx], self.feasible[idx])
+
     def kappa(self):
         """Conditioning sum_i |t_i| / |sum_i t_i| per config (inf for zero traces)."""
         out = np.full(len(self.sign), np.inf)
@@ -160,6 +166,74 @@ class TraceOracle:
         if abs(ov) <= self.zero_tol:      # unit vectors: a symmetry zero in exact arithmetic
             return True, 0, -np.inf
         return True, (1 if ov > 0 else -1), ell + np.log(abs(ov)) - beta * E0
+
+    # -- conditioning ----------------------------------------------------------
+    def path_condition(self, tau, flavor, dagger, r: int):
+        """Cut-point condition numbers kappa_k = 1 / |<L_k|R_k>| of one path.
+
+        Cut the operator product of Eq.(2) just before operator k:
+        t_r = <E_i| A_k B_k |E_i>, with R_k = B_k|E_i> / |B_k|E_i>| the
+        propagated vector the forward pass holds there and
+        L_k = A_k^T|E_i> / |A_k^T|E_i>| the closing state carried backwards to
+        the same point.  Replacing R_k by R_k + delta (|delta| <= eps) changes
+        t_r by the relative amount <L_k|delta> / <L_k|R_k>, at most
+        eps * kappa_k; a method whose propagations are accurate to eps in
+        norm is therefore accurate to about eps * sum_k kappa_k on this path
+        (first order).  Returns the array over k = 0..n-1, or None for a path
+        that is zero (sector-infeasible or a symmetry zero)."""
+        feas, sg, _ = self.path(tau, flavor, dagger, 0.0, r)
+        nops = len(tau)
+        if not feas or sg == 0:
+            return None
+        if nops == 0:
+            return np.zeros(0)
+        b0 = int(self.R.block[r])
+        ei = self.spec.V[b0][:, int(self.R.index[r])]
+        R, blocks, mats = [], [], []
+        v, b = ei.copy(), b0
+        for k in range(nops):
+            if k > 0:
+                v, _ = self.propagate_log(b, v, float(tau[k] - tau[k - 1]))
+            R.append(v.copy())
+            blocks.append(b)
+            b, M = self.op_block(int(flavor[k]), int(dagger[k]), b)
+            mats.append(M)
+            v = M @ v
+            v = v / np.linalg.norm(v)
+        kap = np.empty(nops)
+        u = ei.copy()
+        for k in range(nops - 1, -1, -1):
+            u = mats[k].T @ u
+            u = u / np.linalg.norm(u)
+            ov = abs(float(u @ R[k]))
+            kap[k] = np.inf if ov == 0.0 else 1.0 / ov
+            if k > 0:
+                # exp(-dtau H_b) is symmetric: the backward step is the same propagation
+                u, _ = self.propagate_log(blocks[k], u, float(tau[k] - tau[k - 1]))
+        return kap
+
+    def condition(self, batch, result: TraceResult, configs=None) -> np.ndarray:
+        """Per configuration: sum_i |t_i| K_i / |sum_i t_i| with K_i = sum_k kappa_k
+        of path i, the first-order amplification of per-propagation relative
+        errors into the relative error of Tr_R (1 for an empty configuration,
+        0 for an exact zero, inf for a cancelling sum)."""
+        idx = list(range(batch.n_configs) if configs is None else configs)
+        out = np.zeros(len(idx))
+        for j, c in enumerate(idx):
+            if result.sign[j] == 0:
+                continue
+            tau, fl, dg = batch.config(c)
+            lg = result.contrib_log[j]
+            m = np.max(lg[result.contrib_sign[j] != 0])
+            acc = 0.0
+            for r in range(len(lg)):
+                if result.contrib_sign[j, r] == 0:
+                    continue
+                kap = self.path_condition(tau, fl, dg, r)
+                K = max(1.0, float(np.sum(kap))) if kap is not None else 1.0
+                acc += np.exp(lg[r] - m) * K
+            out[j] = acc * np.exp(m - result.log_abs[j])
+        return out
 
     # -- the batch -----------------------------------------------------------
     def trace_batch(self, batch, configs=None) -> TraceResult:

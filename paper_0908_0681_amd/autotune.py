@@ -60,7 +60,20 @@ def tune(k: int, reps: int = 3, n_configs: int | None = None) -> dict:
         torch.cuda.synchronize()
         results[name] = (time.perf_counter() - t0) / reps * 1e3
     best = min(results, key=results.get)
-    return {"workload": w.name, "best": best, "ms": results}
+    # launch schedule of the best variant: operators per path-kernel launch
+    model.set_variant(hyb.variant_names().index(best))
+    chunks = {}
+    for chunk in (1, 8, 32, 0):
+        model.set_chunk(chunk)
+        model.trace_batch_device(dev, batch.beta, out)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            model.trace_batch_device(dev, batch.beta, out)
+        torch.cuda.synchronize()
+        chunks[chunk] = (time.perf_counter() - t0) / reps * 1e3
+    best_chunk = min(chunks, key=chunks.get)
+    return {"workload": w.name, "best": best, "ms": results, "chunk": best_chunk, "chunk_ms": chunks}
 
 
 def main():
@@ -75,7 +88,8 @@ def main():
     for k in a.workloads:
         r = tune(k, a.reps)
         w = I.workload(k)
-        cache[cache_key(arch, w.params.n_orb, w.precision)] = {"variant": r["best"], "ms": r["ms"]}
+        cache[cache_key(arch, w.params.n_orb, w.precision)] = {
+            "variant": r["best"], "ms": r["ms"], "chunk": r["chunk"], "chunk_ms": r["chunk_ms"]}
         print(json.dumps(r), flush=True)
     with open(a.out, "w") as f:
         json.dump(cache, f, indent=1, sort_keys=True)

@@ -70,6 +70,7 @@ struct hyb_model {
   bool uploaded = false;
   hyb::DeviceModel dev;
   int variant = -1;         // trace kernel variant (-1 = automatic)
+  int chunk = 1;            // operators per path-step launch (1 = one launch per step kind)
   bool timing = false;
   float last_ms[7] = {0, 0, 0, 0, 0, 0, 0};
   void* events[4] = {nullptr, nullptr, nullptr, nullptr};

@@ -49,6 +49,24 @@ __global__ __launch_bounds__(NT) void k_path_prop(TraceParams P, int k) {
   path_prop<VT, NT, RPT, MAXM>(P, blockIdx.x, k, S);
 }
 
+// Operators [k0, k1) of every path, one workgroup per path: the propagation before
+// operator k (k > 0) and the operator itself, exactly as the single-step kernels,
+// separated by workgroup barriers (the path's vector passes through global memory).
+template <typename VT, int NT, int RPT, int MAXM>
+__global__ __launch_bounds__(NT) void k_path_chunk(TraceParams P, int k0, int k1) {
+  __shared__ typename PathEngine<VT, NT, RPT, MAXM>::Smem S;
+  __shared__ double red[NT / 64];
+  const int w = blockIdx.x;
+  for (int k = k0; k < k1; ++k) {
+    if (k > 0) {
+      path_prop<VT, NT, RPT, MAXM>(P, w, k, S);
+      __syncthreads();
+    }
+    path_op<VT, NT, RPT>(P, w, k, red);
+    __syncthreads();
+  }
+}
+
 template <typename VT, int NT, int RPT>
 __global__ __launch_bounds__(NT) void k_path_final(TraceParams P) {
   __shared__ double red[NT / 64];
@@ -131,6 +149,7 @@ struct Variant {
   const void* step_fn;   // k_path_prop
   const void* final_fn;  // k_path_final
   const void* prop_fn;   // k_propagate (parity hook)
+  const void* chunk_fn;  // k_path_chunk
 };
 
 #define VARIANT(VT, NT, RPT, MAXM, NAME)                                                      \
@@ -138,7 +157,8 @@ struct Variant {
    reinterpret_cast<const void*>(&k_path_op<VT, NT, RPT>),                                    \
    reinterpret_cast<const void*>(&k_path_prop<VT, NT, RPT, MAXM>),                            \
    reinterpret_cast<const void*>(&k_path_final<VT, NT, RPT>),                                 \
-   reinterpret_cast<const void*>(&k_propagate<VT, NT, RPT, MAXM>)}
+   reinterpret_cast<const void*>(&k_propagate<VT, NT, RPT, MAXM>),                            \
+   reinterpret_cast<const void*>(&k_path_chunk<VT, NT, RPT, MAXM>)}
 
 static const Variant kVariants[] = {
     VARIANT(double, 64, 1, 12, "f64_nt64_r1_m12"),
@@ -342,6 +362,19 @@ int hyb_get_trace_variant(const hyb_model* m, int32_t* v) {
   return HYB_OK;
 }
 
+int hyb_set_chunk(hyb_model* m, int32_t chunk) {
+  if (!m) return set_error(HYB_E_ARG, "NULL model");
+  if (chunk < 0) return set_error(HYB_E_ARG, "chunk must be >= 0");
+  m->chunk = chunk == 0 ? (1 << 30) : chunk;
+  return HYB_OK;
+}
+
+int hyb_get_chunk(const hyb_model* m, int32_t* chunk) {
+  if (!m || !chunk) return set_error(HYB_E_ARG, "NULL argument");
+  *chunk = m->chunk;
+  return HYB_OK;
+}
+
 int hyb_set_timing(hyb_model* m, int32_t on) {
   if (!m) return set_error(HYB_E_ARG, "NULL model");
   m->timing = on != 0;
@@ -501,16 +534,29 @@ int hyb_trace_batch(hyb_model* m, const hyb_config_batch* cfg, double beta, hyb_
       m->step_events.push_back(e);
     }
     auto ev_at = [&](size_t i) { return reinterpret_cast<hipEvent_t>(m->step_events[i]); };
-    for (int k = 0; k < max_ops; ++k) {
-      void* ak[] = {&P, &k};
-      if (k > 0) {
-        if (m->timing) HIP_TRY(hipEventRecord(ev_at(4 * k), s));
-        HIP_TRY(hipLaunchKernel(V.step_fn, dim3(unsigned(nwork)), dim3(V.nt), ak, 0, s));
-        if (m->timing) HIP_TRY(hipEventRecord(ev_at(4 * k + 1), s));
+    if (m->chunk <= 1) {
+      for (int k = 0; k < max_ops; ++k) {
+        void* ak[] = {&P, &k};
+        if (k > 0) {
+          if (m->timing) HIP_TRY(hipEventRecord(ev_at(4 * k), s));
+          HIP_TRY(hipLaunchKernel(V.step_fn, dim3(unsigned(nwork)), dim3(V.nt), ak, 0, s));
+          if (m->timing) HIP_TRY(hipEventRecord(ev_at(4 * k + 1), s));
+        }
+        if (m->timing) HIP_TRY(hipEventRecord(ev_at(4 * k + 2), s));
+        HIP_TRY(hipLaunchKernel(V.op_fn, dim3(unsigned(nwork)), dim3(V.nt), ak, 0, s));
+        if (m->timing) HIP_TRY(hipEventRecord(ev_at(4 * k + 3), s));
       }
-      if (m->timing) HIP_TRY(hipEventRecord(ev_at(4 * k + 2), s));
-      HIP_TRY(hipLaunchKernel(V.op_fn, dim3(unsigned(nwork)), dim3(V.nt), ak, 0, s));
-      if (m->timing) HIP_TRY(hipEventRecord(ev_at(4 * k + 3), s));
+    } else {
+      // chunks of operators per launch; the events bracket whole chunks (reported
+      // as propagation time: the chunk kernel spends nearly all of it there)
+      int c = 0;
+      for (int k0 = 0; k0 < max_ops; k0 += m->chunk, ++c) {
+        int k1 = std::min(max_ops, k0 + m->chunk);
+        void* ak[] = {&P, &k0, &k1};
+        if (m->timing) HIP_TRY(hipEventRecord(ev_at(4 * c), s));
+        HIP_TRY(hipLaunchKernel(V.chunk_fn, dim3(unsigned(nwork)), dim3(V.nt), ak, 0, s));
+        if (m->timing) HIP_TRY(hipEventRecord(ev_at(4 * c + 1), s));
+      }
     }
     HIP_TRY(hipLaunchKernel(V.final_fn, dim3(unsigned(nwork)), dim3(V.nt), a0, 0, s));
   }
@@ -538,7 +584,15 @@ int hyb_trace_batch(hyb_model* m, const hyb_config_batch* cfg, double beta, hyb_
     HIP_TRY(hipEventElapsedTime(&m->last_ms[2], ev[2], ev[3]));
     float prop = 0.f, op = 0.f;
     int nprop = 0, nop = 0;
-    if (nwork > 0)
+    if (nwork > 0 && m->chunk > 1) {
+      for (int c = 0, k0 = 0; k0 < max_ops; k0 += m->chunk, ++c) {
+        float t = 0.f;
+        HIP_TRY(hipEventElapsedTime(&t, reinterpret_cast<hipEvent_t>(m->step_events[4 * c]),
+                                    reinterpret_cast<hipEvent_t>(m->step_events[4 * c + 1])));
+        prop += t;
+        ++nprop;
+      }
+    } else if (nwork > 0)
       for (int k = 0; k < max_ops; ++k) {
         float t = 0.f;
         if (k > 0) {

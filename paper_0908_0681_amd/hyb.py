@@ -74,6 +74,8 @@ _SIGS = {
     "hyb_get_trace_variant": (C.c_int, [_P, _P]),
     "hyb_trace_variant_count": (C.c_int, [_P]),
     "hyb_trace_variant_name": (C.c_int, [C.c_int32, C.c_char_p, C.c_size_t]),
+    "hyb_set_chunk": (C.c_int, [_P, C.c_int32]),
+    "hyb_get_chunk": (C.c_int, [_P, _P]),
     "hyb_set_timing": (C.c_int, [_P, C.c_int32]),
     "hyb_last_timing": (C.c_int, [_P, _P]),
     "hyb_block_spmm": (C.c_int, [_P, C.c_int32, C.c_int64, _P, _P, _P]),
@@ -254,6 +256,14 @@ class Model:
         _check(lib().hyb_get_trace_variant(self.h, C.byref(v)))
         return v.value
 
+    def set_chunk(self, chunk):
+        _check(lib().hyb_set_chunk(self.h, chunk))
+
+    def chunk(self):
+        c = C.c_int32()
+        _check(lib().hyb_get_chunk(self.h, C.byref(c)))
+        return c.value
+
     def set_timing(self, on=True):
         _check(lib().hyb_set_timing(self.h, 1 if on else 0))
 
@@ -318,10 +328,13 @@ def model_for_workload(w, upload=True, use_cache=True, **kw):
             import torch
             from . import autotune
             key = autotune.cache_key(autotune.gpu_arch(), w.params.n_orb, m.precision)
-            name = autotune.load_cache().get(key, {}).get("variant")
+            entry = autotune.load_cache().get(key, {})
+            name = entry.get("variant")
             if name in variant_names():
                 m.set_variant(variant_names().index(name))
                 _log(f"autotuned variant {name} for {key}")
+            if "chunk" in entry:
+                m.set_chunk(int(entry["chunk"]))
         except HybError:
             pass
     return m

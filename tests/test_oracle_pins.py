@@ -403,6 +403,46 @@ def test_bruteforce_mpmath_50_digits():
     close_log(int(r.sign[0]), r.log_abs[0], s, l, 1e-13)
 
 
+def test_path_condition_matches_full_space_cuts():
+    """kappa_k of every path against the full Fock-space factorisation
+    t_i = <e_i| A_k B_k |e_i> (dense expm of the whole H, no blocks, no log
+    scaling): kappa_k = |A_k^T e_i| |B_k e_i| / |t_i|."""
+    p = I.kanamori(3, 4.0, 1.0, I.mu_half(3, 4.0, 1.0), delta=I.crystal_field(3, 0.3, 7))
+    beta, window = 10.0, 1e-9
+    o = T.build(p, window)
+    ops = o.ops
+    H = Hm.kanamori_full(p, ops=ops).toarray()
+    dimF = H.shape[0]
+    b = I.random_batch(43, 3, 12, beta, 1.0, "random")
+    r = o.trace_batch(b)
+    checked = 0
+    for c in range(b.n_configs):
+        tau, fl, dg = b.config(c)
+        n = len(tau)
+        for ri in range(len(o.R.block)):
+            if r.contrib_sign[c, ri] == 0 or n == 0:
+                continue
+            kap = o.path_condition(tau, fl, dg, ri)
+            e = np.zeros(dimF)
+            bk = int(o.R.block[ri])
+            e[np.asarray(o.spec.states[bk])] = o.spec.V[bk][:, int(o.R.index[ri])]
+            Os = [ops.op(int(fl[k]), int(dg[k])).toarray() for k in range(n)]
+            for k in range(n):
+                B = sla.expm(-H * tau[0])
+                for j in range(k):
+                    B = sla.expm(-H * (tau[j + 1] - tau[j])) @ Os[j] @ B
+                A = sla.expm(-H * (beta - tau[-1]))
+                for j in range(n - 1, k - 1, -1):
+                    A = A @ Os[j]
+                    if j > k:
+                        A = A @ sla.expm(-H * (tau[j] - tau[j - 1]))
+                t = e @ A @ B @ e
+                want = np.linalg.norm(A.T @ e) * np.linalg.norm(B @ e) / abs(t)
+                assert kap[k] == pytest.approx(want, rel=1e-8), (c, ri, k)
+                checked += 1
+    assert checked > 20
+
+
 # ---------------------------------------------------------------------------
 # invariances of the full trace
 # ---------------------------------------------------------------------------
