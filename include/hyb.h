@@ -92,7 +92,7 @@ typedef struct {
 /* Builds the bit-encoded basis, the (n_up, n_dn) blocks, H_loc per block (Eq.(4)
  * with spin-flip and pair-hopping summed once per ordered orbital pair a != b),
  * the spectrum of every block by dense FP64 Householder tridiagonalisation and
- * implicit QL (Sec. III step 1, full diagonalisation), E0 and the retained set
+ * implicit QR with Wilkinson shifts (Sec. III step 1, full diagonalisation), E0 and the retained set
  * (step 2).  Host memory only; no GPU is touched.  *out receives a new handle. */
 int hyb_model_create(const hyb_model_params* p, hyb_model** out);
 

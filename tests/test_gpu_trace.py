@@ -188,7 +188,11 @@ def test_five_orbital_structural_zeros(w1):
     r = m.trace_batch(b)
     ref = o.trace_batch(b)
     compare(r, ref, 1e-10, o, b)
-    assert np.sum(~ref.feasible.any(axis=1)) > b.n_configs // 2   # the case is exercised
+    # every kind of case is exercised: no feasible sector path, feasible paths
+    # that are all symmetry zeros, and nonzero traces
+    structural = ~ref.feasible.any(axis=1)
+    symmetry = ref.feasible.any(axis=1) & (ref.sign == 0)
+    assert structural.sum() >= 10 and symmetry.sum() >= 10 and (ref.sign != 0).sum() >= 10
 
 
 def test_seven_orbital_mixed_parity(w2):
