@@ -202,3 +202,112 @@ def workload(k: int) -> Workload:
         return Workload("kanamori-7orb-b40", p, 40.0, 1024, 6.0, 1002, "mixed", 1e-5,
                         krylov_max=20, krylov_tol=1e-7)
     raise ValueError(k)
+
+
+# --------------------------------------------------------------------------
+# bath and Monte Carlo inputs
+# --------------------------------------------------------------------------
+
+def semicircle_delta(beta: float, n_tau: int, D: float = 2.0, t: float = 1.0,
+                     n_quad: int = 6000) -> np.ndarray:
+    """Hybridization function of a semicircular bath, tabulated on a uniform grid.
+
+    Delta(tau) = t^2 G_sc(tau) with G_sc(tau) = -int rho(e) e^{-tau e} / (1 + e^{-beta e}) de,
+    rho(e) = 2 / (pi D^2) sqrt(D^2 - e^2) (the bandwidth-4 semicircle of Sec. IV.A for
+    D = 2), at tau_k = k beta / n_tau, k = 0..n_tau (k = 0 is 0^+, k = n_tau is beta^-).
+    This is an *input* of the impurity solver (in a DMFT loop it would come from the
+    self-consistency); the solver interpolates the table linearly and extends it
+    antiperiodically.  Gauss-Chebyshev quadrature of the second kind with n_quad nodes.
+    """
+    i = np.arange(1, n_quad + 1)
+    x = np.cos(i * np.pi / (n_quad + 1))
+    w = np.pi / (n_quad + 1) * np.sin(i * np.pi / (n_quad + 1)) ** 2
+    e = D * x
+    taus = np.arange(n_tau + 1) * (beta / n_tau)
+    out = np.empty(n_tau + 1)
+    pos = e > 0
+    for k, tau in enumerate(taus):
+        # overflow-free Fermi-weighted exponential on both sides of the band centre
+        g = np.empty_like(e)
+        g[pos] = np.exp(-tau * e[pos]) / (1.0 + np.exp(-beta * e[pos]))
+        g[~pos] = np.exp((beta - tau) * e[~pos]) / (np.exp(beta * e[~pos]) + 1.0)
+        out[k] = -(2.0 / np.pi) * np.sum(w * g) * t * t
+    return out
+
+
+@dataclass
+class McSetup:
+    name: str
+    workload: Workload
+    n_chains: int
+    n_tau_delta: int
+    delta: np.ndarray          # [n_tau_delta + 1]
+    init_seed: int
+    max_init_pairs: int        # chains start at total pair numbers uniform in 0..max
+    kmax_flavor: int           # capacity per flavor (pairs)
+    seed: int                  # counter-based generator key of the chains
+
+
+def mc_setup(k: int = 3, n_chains: int | None = None) -> McSetup:
+    """Monte Carlo workloads.  k = 3: the 5-orbital model of workload 1 coupled to a
+    semicircular bath (D = 2, t = 1), 256 chains whose initial total pair numbers are
+    uniform in 0..200 (a scheduling stress).  k = 5: one orbital, U = 0, eps = 0, beta = 10
+    (the non-interacting check: G(tau) must equal G_sc(tau)).  k = 6: the 2-orbital model
+    of workload 0 with the bath, small chains for trajectory parity."""
+    if k == 3:
+        w = workload(1)
+        n = 256 if n_chains is None else n_chains
+        return McSetup("kanamori-5orb-b50-mc", w, n, 4096, semicircle_delta(w.beta, 4096), 3003, 200, 48, 7)
+    if k == 5:
+        p = kanamori(1, U=0.0, J=0.0, mu=0.0)
+        w = Workload("free-1orb-b10", p, 10.0, 0, 0.0, 0, "fp64", -1.0)
+        n = 64 if n_chains is None else n_chains
+        return McSetup("free-1orb-b10-mc", w, n, 1000, semicircle_delta(10.0, 1000), 3005, 0, 48, 11)
+    if k == 6:
+        w = workload(0)
+        n = 8 if n_chains is None else n_chains
+        return McSetup("kanamori-2orb-b10-mc", w, n, 1000, semicircle_delta(w.beta, 1000), 3006, 12, 32, 13)
+    raise ValueError(k)
+
+
+def mc_initial_configs(setup: McSetup):
+    """Per chain: (cre, ann) with cre[f] / ann[f] the creator / annihilator times of
+    flavor f in label order (the i-th creator in time is paired with the i-th
+    annihilator).  Total pair number uniform in 0..max_init_pairs, spread over the
+    flavors uniformly; per flavor the operators alternate in time, starting with c if
+    the flavor is occupied in a reference Fock state (single occupancy, random spins)."""
+    n_orb = setup.workload.params.n_orb
+    F, beta = 2 * n_orb, setup.workload.beta
+    rng = np.random.default_rng(setup.init_seed)
+    chains = []
+    for _ in range(setup.n_chains):
+        K = int(rng.integers(0, setup.max_init_pairs + 1))
+        kf = np.bincount(rng.integers(0, F, size=K), minlength=F)
+        kf = np.minimum(kf, setup.kmax_flavor)
+        spins = rng.integers(0, 2, size=n_orb)
+        occ = np.zeros(F, dtype=bool)
+        for a in range(n_orb):
+            occ[a + n_orb * spins[a]] = True
+        cre, ann = [], []
+        for f in range(F):
+            ts = np.sort(rng.uniform(0.0, beta, size=2 * kf[f]))
+            if occ[f]:       # c first: annihilators at even positions
+                ann.append(ts[0::2].copy()); cre.append(ts[1::2].copy())
+            else:
+                cre.append(ts[0::2].copy()); ann.append(ts[1::2].copy())
+        chains.append((cre, ann))
+    return chains
+
+
+def mc_merged(cre, ann):
+    """Time-ordered operator list (tau, flavor, dagger) of a per-flavor pair state."""
+    taus, fls, dgs = [], [], []
+    for f in range(len(cre)):
+        taus += [np.asarray(cre[f]), np.asarray(ann[f])]
+        fls += [np.full(len(cre[f]), f, np.int16), np.full(len(ann[f]), f, np.int16)]
+        dgs += [np.ones(len(cre[f]), np.int8), np.zeros(len(ann[f]), np.int8)]
+    tau = np.concatenate(taus) if taus else np.zeros(0)
+    fl = np.concatenate(fls) if fls else np.zeros(0, np.int16)
+    dg = np.concatenate(dgs) if dgs else np.zeros(0, np.int8)
+    o = np.argsort(tau, kind="stable")
+    return tau[o], fl[o], dg[o]
