@@ -112,6 +112,38 @@ def sum_intervals(batch, out, torch):
     return int(np.sum(feas * np.maximum(nops - 1, 0)))
 
 
+def measure_mc(torch, hyb, I, moves=40, warm=10):
+    """Chain-moves per second of the Monte Carlo layer on the 5-orbital model with
+    a semicircular bath: 256 chains started at total pair numbers uniform in
+    0..200, one pair insertion or removal per chain and move, each with a Krylov
+    trace of the proposed configuration and O(k^2) determinant updates."""
+    setup = I.mc_setup(3)
+    w = setup.workload
+    m = hyb.model_for_workload(w)
+    mc = hyb.MC(m, setup.n_chains, w.beta, setup.delta, kmax=setup.kmax_flavor, nmax_ops=512,
+                seed=setup.seed, n_tau=200, meas_every=10)
+    chains = I.mc_initial_configs(setup)
+    # a start whose trace vanishes is replaced by the empty configuration
+    r = m.trace_batch(I.from_lists([I.mc_merged(cre, ann) for cre, ann in chains], w.beta))
+    F = 2 * w.params.n_orb
+    chains = [ch if r.sign[c] != 0 else ([[]] * F, [[]] * F) for c, ch in enumerate(chains)]
+    mc.set_configs(chains)
+    mc.sweep(warm)
+    mc.reset_measurements()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    mc.sweep(moves)
+    dt = time.perf_counter() - t0
+    st = mc.stats()
+    acc = (st["insert_accepted"] + st["remove_accepted"]) / max(1, st["moves"])
+    res = {"workload": setup.name, "n_chains": setup.n_chains, "moves": moves,
+           "chain_moves_per_s": setup.n_chains * moves / dt, "ms_per_move": dt / moves * 1e3,
+           "acceptance": acc, "mean_order": st["order_sum"] / max(1, st["moves"]),
+           "sign_avg": st["sign_sum"] / max(1, st["moves"])}
+    mc.close()
+    return res
+
+
 def cpu_baseline(k, n_sample):
     """The FP64 oracle as it stands, on the first n_sample configurations."""
     import numpy as np
@@ -142,6 +174,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-sample", type=int, default=192)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-mc", action="store_true", help="skip the Monte Carlo sweep timing")
     ap.add_argument("--seven", action="store_true", help="also time the 7-orbital mixed workload")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (3 times) and exit: the reference "
@@ -207,6 +240,8 @@ def main():
         line["detail"]["kanamori-7orb-b40"] = {k: r7[k] for k in (
             "traces_per_s", "ms_per_step", "prop_ms", "prop_launches", "prop_bytes", "mean_krylov_depth",
             "feasible_paths")}
+    if not a.no_mc:
+        line["detail"]["mc"] = measure_mc(torch, hyb, I)
     if not a.no_cpu:
         line["cpu_baseline"] = cpu_baseline(1, a.cpu_sample)
     print(json.dumps(line), flush=True)

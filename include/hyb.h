@@ -217,6 +217,89 @@ int hyb_last_timing(const hyb_model* m, float* out7);
  * streams from HBM in one pass.  n_vec must be a multiple of 16. */
 int hyb_block_spmm(hyb_model* m, int32_t block, int64_t n_vec, const float* X, float* Y, void* stream);
 
+/* ---- Monte Carlo sampling of the expansion (Sec. II) ------------------------ */
+
+/* Weight of a configuration (Eq.(2) with a diagonal hybridization):
+ *   w = s_perm * Tr_R(literal time-ordered product) * prod_f det A_f,
+ *   A_f[i][j] = Delta(tau'_{f,i} - tau_{f,j}),
+ * row i = i-th creator of flavor f, column j = its j-th annihilator (label order).
+ * s_perm is the sign of the permutation taking the canonical string (flavor by
+ * flavor, label by label: c_f(tau_{f,i}) c^dag_f(tau'_{f,i})) to descending time
+ * order, i.e. the fermionic sign of the time-ordering operator.  Delta is given as a
+ * table on a uniform grid of [0, beta], interpolated linearly and extended
+ * antiperiodically (Delta(tau - beta) = -Delta(tau)).
+ *
+ * Moves (one per chain per step): flavor f = floor(u0 F); if u1 < 1/2 insert a
+ * creator at ts = u2 beta and an annihilator at te = ts + u3 beta (mod beta) as label
+ * k_f (acceptance factor beta^2 / (k_f+1)^2), else remove creator label floor(u2 k_f)
+ * and annihilator label floor(u3 k_f), filling each hole with the last label
+ * (factor k_f^2 / beta^2); accept when u4 < |w'/w| * factor.  u0..u5 come from
+ * Philox4x32-10 (Salmon et al., SC'11) with counter (move low word, move high word,
+ * chain, call 0..2) and key (seed low word, seed high word); a double is
+ * ((a >> 5) 2^26 + (b >> 6)) / 2^53 from two output words.  Determinant ratios
+ * and inverse updates are O(k^2) (Sec. II, fast updates); every move evaluates one
+ * Krylov trace per chain through the batched trace path.
+ *
+ * G(tau) estimator (per flavor, after every meas_every-th move):
+ *   G_f(tau) = -(1/beta) < sum_ij M_f[j][i] delta~(tau, tau_{f,j} - tau'_{f,i}) >,
+ * M_f = A_f^{-1}; a negative difference is shifted by +beta and enters with a minus
+ * sign; histogram of n_tau bins on [0, beta); samples weighted by sign(w). */
+typedef struct {
+  int32_t n_chains;
+  double beta;
+  int32_t n_delta;        /* intervals of the Delta table (table has n_delta + 1 values) */
+  const double* delta;    /* host, [n_delta + 1]: Delta(k beta / n_delta); copied */
+  int32_t kmax;           /* pair capacity per flavor, 1..63 */
+  int32_t nmax_ops;       /* operator capacity per configuration, 2..4096 */
+  uint64_t seed;          /* generator key */
+  int32_t n_tau;          /* G(tau) bins */
+  int32_t meas_every;     /* measure after every meas_every-th move */
+  int32_t moves_per_sweep;
+} hyb_mc_params;
+
+typedef struct {
+  int64_t insert_proposed, insert_accepted, remove_proposed, remove_accepted;
+  int64_t impossible;     /* capacity reached or flavor empty */
+  int64_t zero_weight;    /* proposals whose weight was zero (trace zero, time tie) */
+  int64_t moves;          /* chain-moves counted */
+  double order_sum;       /* sum over chain-moves of the total pair number */
+  double sign_sum;        /* sum over chain-moves of sign(w) */
+} hyb_mc_stats;
+
+typedef struct hyb_mc hyb_mc;
+
+/* Allocates n_chains chains on the model's device, all starting from the empty
+ * configuration (weight Tr_R of no operators > 0).  The model must stay alive and
+ * uploaded.  Errors: HYB_E_ARG (parameters), HYB_E_STATE, HYB_E_OOM, HYB_E_HIP. */
+int hyb_mc_create(hyb_model* m, const hyb_mc_params* p, hyb_mc** out);
+int hyb_mc_destroy(hyb_mc* mc);
+
+/* Replaces every chain's configuration (host arrays): k [n_chains][F] pair numbers,
+ * cre / ann [n_chains][F][kmax] creator / annihilator times in label order.  Builds
+ * M_f = A_f^{-1} by LU on the host, traces the configurations, and resets the move
+ * counter, statistics and accumulators.  HYB_E_ARG for a zero weight, a singular
+ * A_f or a capacity overflow; HYB_E_UNSORTED for equal or out-of-range times. */
+int hyb_mc_set_configs(hyb_mc* mc, const int32_t* k, const double* cre, const double* ann, void* stream);
+
+/* n_sweeps * moves_per_sweep moves of every chain on `stream`; returns after the
+ * stream drained.  HYB_E_NOCONV / HYB_E_NONFINITE if a trace inside failed. */
+int hyb_mc_sweep(hyb_mc* mc, int32_t n_sweeps, void* stream);
+
+/* Current state (host outputs, each may be NULL): k, cre, ann as in set_configs,
+ * M [n_chains][F][kmax][kmax] (row = annihilator label, column = creator label),
+ * logw = log|w| and sign = sign(w) per chain. */
+int hyb_mc_get_state(const hyb_mc* mc, int32_t* k, double* cre, double* ann, double* M, double* logw,
+                     int8_t* sign, void* stream);
+int hyb_mc_get_stats(const hyb_mc* mc, hyb_mc_stats* out, void* stream);
+/* Raw per-chain accumulators: gacc [n_chains][F][n_tau] = sum of sign * signed M
+ * entries per bin, meas_sign [n_chains] = sum of signs, n_meas [n_chains]. */
+int hyb_mc_get_accumulators(const hyb_mc* mc, double* gacc, double* meas_sign, int64_t* n_meas, void* stream);
+/* G [F][n_tau] over all chains: -sum gacc / (beta * (beta / n_tau) * sum meas_sign);
+ * *sign_avg = <sign>.  HYB_E_STATE before any measurement. */
+int hyb_mc_measure(const hyb_mc* mc, double* G, double* sign_avg, void* stream);
+int hyb_mc_reset_measurements(hyb_mc* mc, void* stream);
+int hyb_mc_step_count(const hyb_mc* mc, int64_t* step);
+
 /* ---- misc ------------------------------------------------------------------ */
 const char* hyb_last_error(void);
 const char* hyb_version(void);

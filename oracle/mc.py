@@ -177,6 +177,7 @@ class Chain:
         self.cre = [list(map(float, c)) for c in cre]
         self.ann = [list(map(float, a)) for a in ann]
         self.sign, self.logw = weight(tr, table, beta, self.cre, self.ann)
+        self.last_margin = np.inf
         if self.sign == 0:
             raise ValueError("initial configuration has zero weight")
 
@@ -222,6 +223,9 @@ class Chain:
         kind, cre, ann, s, lw, log_ratio = self.propose(u)
         if kind == 0 or s == 0:
             return kind, False
+        # distance of the decision from its threshold (a replay in another
+        # floating-point order can only differ when this is at rounding level)
+        self.last_margin = abs(np.log(u[4]) - log_ratio) if u[4] > 0.0 else np.inf
         if u[4] < np.exp(log_ratio):
             self.cre, self.ann, self.sign, self.logw = cre, ann, s, lw
             return kind, True

@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libhyb.so")
 
-SOURCES = ["model.cpp", "eigen.cpp", "trace.hip", "spmm.hip"]
+SOURCES = ["model.cpp", "eigen.cpp", "trace.hip", "spmm.hip", "mc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
@@ -27,11 +27,17 @@ DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-p
           "-munsafe-fp-atomics"]
 
 
+# The Monte Carlo code rounds every operation separately (no fused multiply-add,
+# also inside inlined library helpers), so that operator times and acceptance
+# ratios are bitwise reproducible by any IEEE 754 implementation.
+EXTRA = {"mc.hip": ["-ffp-contract=off"]}
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, src + ".o")
     path = os.path.join(CSRC, src)
     if src.endswith(".hip"):
-        cmd = [HIPCC, "-x", "hip", *DEVICE, *COMMON, "-c", path, "-o", obj]
+        cmd = [HIPCC, "-x", "hip", *DEVICE, *COMMON, *EXTRA.get(src, []), "-c", path, "-o", obj]
     else:
         cmd = [HIPCC, *COMMON, "-march=x86-64-v3", "-c", path, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)

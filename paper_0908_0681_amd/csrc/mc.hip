@@ -1,0 +1,476 @@
+// Monte Carlo sampling of the hybridization expansion on the device: random pair
+// insertion / removal per flavor (Sec. II), determinant ratios and fast inverse
+// updates in O(k^2) (Sec. II: fast matrix updates), one truncated Krylov trace per
+// chain and move (the batched trace path), Metropolis-Hastings acceptance and
+// the binned G(tau) estimator.
+//
+// Weight of a configuration: w = s_perm * Tr_R(literal time-ordered product)
+// * prod_f det A_f, with A_f[i][j] = Delta(tau'_{f,i} - tau_{f,j}) (row i: the
+// i-th creator of flavor f, column j: its j-th annihilator).  s_perm is the sign
+// of the permutation from the canonical string (flavor by flavor, label by label:
+// c_f(tau_{f,i}) c^dag_f(tau'_{f,i})) to descending time order: the fermionic sign
+// of the time-ordering operator of Eq.(2).  M_f = A_f^{-1} is kept per flavor.
+//
+// Random numbers: Philox4x32-10 (Salmon et al., SC'11) with counter (move low word,
+// move high word, chain, call) and key (seed low word, seed high word).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "hyb_internal.h"
+#include "trace_kernels.h"
+#include "trace_launch.h"
+
+namespace hyb {
+
+#define MC_HIP_TRY(expr)                                                              \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return set_error(HYB_E_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));     \
+  } while (0)
+
+}  // namespace hyb (device code in mc_kernels.h)
+#include "mc_kernels.h"
+namespace hyb {
+
+__global__ __launch_bounds__(64) void k_mc_propose(MCParams Q, int64_t step) {
+  __shared__ double sb[64], sc[64];
+  mc_propose(Q, blockIdx.x, step, sb, sc);
+}
+
+__global__ __launch_bounds__(64) void k_mc_accept(MCParams Q, int64_t step, int measure) {
+  extern __shared__ double canon[];
+  mc_accept(Q, blockIdx.x, step, measure, canon);
+}
+
+}  // namespace hyb
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+
+struct hyb_mc {
+  hyb_model* m = nullptr;
+  hyb_mc_params p{};
+  int F = 0;
+  int64_t step = 0;
+  hyb::MCParams Q{};
+  double* t_log = nullptr;
+  int8_t* t_sign = nullptr;
+  int32_t* err = nullptr;
+  void* trace_ws = nullptr;
+  std::vector<void*> allocs;
+};
+
+namespace {
+
+using namespace hyb;
+
+template <typename T>
+int mc_alloc(hyb_mc* mc, T*& ptr, size_t n) {
+  void* p = nullptr;
+  if (hipMalloc(&p, std::max<size_t>(n, 1) * sizeof(T)) != hipSuccess)
+    return set_error(HYB_E_OOM, "device allocation of %zu bytes", n * sizeof(T));
+  mc->allocs.push_back(p);
+  ptr = static_cast<T*>(p);
+  return 0;
+}
+
+// In-place LU with partial pivoting of an n x n row-major matrix, then its inverse
+// into inv (row-major), log|det| and sign.  Returns false for a singular matrix.
+bool lu_inverse(int n, std::vector<double> a, double* inv, int ld, double& logdet, int& sign) {
+  std::vector<int> piv(n);
+  logdet = 0.0;
+  sign = 1;
+  for (int col = 0; col < n; ++col) {
+    int p = col;
+    for (int r = col + 1; r < n; ++r)
+      if (std::fabs(a[r * n + col]) > std::fabs(a[p * n + col])) p = r;
+    if (a[p * n + col] == 0.0) return false;
+    piv[col] = p;
+    if (p != col) {
+      for (int q = 0; q < n; ++q) std::swap(a[p * n + q], a[col * n + q]);
+      sign = -sign;
+    }
+    const double d = a[col * n + col];
+    logdet += std::log(std::fabs(d));
+    if (d < 0) sign = -sign;
+    for (int r = col + 1; r < n; ++r) {
+      const double l = a[r * n + col] / d;
+      a[r * n + col] = l;
+      for (int q = col + 1; q < n; ++q) a[r * n + q] -= l * a[col * n + q];
+    }
+  }
+  // solve A X = I column by column (P A = L U)
+  std::vector<double> x(n);
+  for (int e = 0; e < n; ++e) {
+    for (int r = 0; r < n; ++r) x[r] = (r == e) ? 1.0 : 0.0;
+    for (int col = 0; col < n; ++col) std::swap(x[col], x[piv[col]]);
+    for (int r = 0; r < n; ++r)
+      for (int q = 0; q < r; ++q) x[r] -= a[r * n + q] * x[q];
+    for (int r = n - 1; r >= 0; --r) {
+      for (int q = r + 1; q < n; ++q) x[r] -= a[r * n + q] * x[q];
+      x[r] /= a[r * n + r];
+    }
+    for (int r = 0; r < n; ++r) inv[r * ld + e] = x[r];
+  }
+  return true;
+}
+
+double delta_host(const hyb_mc* mc, double tau) {
+  double sgn = 1.0;
+  if (tau < 0.0) {
+    tau += mc->p.beta;
+    sgn = -1.0;
+  }
+  const int n = mc->p.n_delta;
+  const double x = tau / mc->p.beta * n;
+  int k = int(x);
+  if (k > n - 1) k = n - 1;
+  const double fr = x - k;
+  return sgn * (mc->p.delta[k] + fr * (mc->p.delta[k + 1] - mc->p.delta[k]));
+}
+
+int run_traces(hyb_mc* mc, hipStream_t s) {
+  return trace_resident(mc->m, mc->p.n_chains, mc->Q.p_begin, mc->Q.p_end, mc->Q.p_tau, mc->Q.p_fl, mc->Q.p_dg,
+                        mc->p.nmax_ops, mc->p.beta, mc->trace_ws, mc->t_log, mc->t_sign, mc->err, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+int hyb_mc_destroy(hyb_mc* mc) {
+  if (!mc) return HYB_OK;
+  for (void* p : mc->allocs) (void)hipFree(p);
+  delete[] mc->p.delta;
+  delete mc;
+  return HYB_OK;
+}
+
+int hyb_mc_create(hyb_model* m, const hyb_mc_params* p, hyb_mc** out) {
+  if (!m || !p || !out) return set_error(HYB_E_ARG, "NULL argument");
+  *out = nullptr;
+  if (!m->uploaded) return set_error(HYB_E_STATE, "model not uploaded to a device");
+  if (p->n_chains < 1 || p->n_chains > (1 << 20)) return set_error(HYB_E_ARG, "n_chains out of range");
+  if (p->kmax < 1 || p->kmax > 63) return set_error(HYB_E_ARG, "kmax must be in 1..63");
+  if (p->nmax_ops < 2 || p->nmax_ops > 4096) return set_error(HYB_E_ARG, "nmax_ops must be in 2..4096");
+  if (p->n_delta < 2 || !p->delta) return set_error(HYB_E_ARG, "Delta table needs n_delta >= 2 intervals");
+  if (!(p->beta > 0.0) || !std::isfinite(p->beta)) return set_error(HYB_E_ARG, "beta must be positive");
+  if (p->n_tau < 1 || p->meas_every < 1 || p->moves_per_sweep < 1)
+    return set_error(HYB_E_ARG, "n_tau, meas_every and moves_per_sweep must be >= 1");
+  for (int i = 0; i <= p->n_delta; ++i)
+    if (!std::isfinite(p->delta[i])) return set_error(HYB_E_ARG, "non-finite Delta table entry %d", i);
+  hyb_mc* mc = new hyb_mc();
+  mc->m = m;
+  mc->p = *p;
+  double* table = new double[p->n_delta + 1];
+  std::memcpy(table, p->delta, sizeof(double) * (p->n_delta + 1));
+  mc->p.delta = table;
+  mc->F = m->F;
+  const int C = p->n_chains, F = m->F, KM = p->kmax, NM = p->nmax_ops;
+  MCParams& Q = mc->Q;
+  Q.n_chains = C;
+  Q.F = F;
+  Q.kmax = KM;
+  Q.nmax = NM;
+  Q.n_delta = p->n_delta;
+  Q.n_tau = p->n_tau;
+  Q.beta = p->beta;
+  Q.key0 = uint32_t(p->seed);
+  Q.key1 = uint32_t(p->seed >> 32);
+  int rc = 0;
+  double* d_delta = nullptr;
+  int64_t* d_begin = nullptr;
+  auto fail = [&](int code) {
+    hyb_mc_destroy(mc);
+    return code;
+  };
+  if ((rc = mc_alloc(mc, d_delta, p->n_delta + 1)) || (rc = mc_alloc(mc, Q.kf, size_t(C) * F)) ||
+      (rc = mc_alloc(mc, Q.cre, size_t(C) * F * KM)) || (rc = mc_alloc(mc, Q.ann, size_t(C) * F * KM)) ||
+      (rc = mc_alloc(mc, Q.M, size_t(C) * F * KM * KM)) || (rc = mc_alloc(mc, Q.cur_n, C)) ||
+      (rc = mc_alloc(mc, Q.cur_tau, size_t(C) * NM)) || (rc = mc_alloc(mc, Q.cur_fl, size_t(C) * NM)) ||
+      (rc = mc_alloc(mc, Q.cur_dg, size_t(C) * NM)) || (rc = mc_alloc(mc, d_begin, C)) ||
+      (rc = mc_alloc(mc, Q.p_end, C)) || (rc = mc_alloc(mc, Q.p_tau, size_t(C) * NM)) ||
+      (rc = mc_alloc(mc, Q.p_fl, size_t(C) * NM)) || (rc = mc_alloc(mc, Q.p_dg, size_t(C) * NM)) ||
+      (rc = mc_alloc(mc, Q.mv, C)) || (rc = mc_alloc(mc, Q.uvec, size_t(C) * KM)) ||
+      (rc = mc_alloc(mc, Q.vvec, size_t(C) * KM)) || (rc = mc_alloc(mc, Q.cur_logtr, C)) ||
+      (rc = mc_alloc(mc, Q.cur_signtr, C)) || (rc = mc_alloc(mc, Q.cur_logdet, C)) ||
+      (rc = mc_alloc(mc, Q.cur_signdet, C)) || (rc = mc_alloc(mc, Q.cur_sign, C)) ||
+      (rc = mc_alloc(mc, mc->t_log, C)) || (rc = mc_alloc(mc, mc->t_sign, C)) ||
+      (rc = mc_alloc(mc, Q.stats, size_t(C) * ST_N)) || (rc = mc_alloc(mc, Q.sign_sum, C)) ||
+      (rc = mc_alloc(mc, Q.gacc, size_t(C) * F * p->n_tau)) || (rc = mc_alloc(mc, Q.meas_sign, C)) ||
+      (rc = mc_alloc(mc, Q.n_meas, C)) || (rc = mc_alloc(mc, mc->err, 1)))
+    return fail(rc);
+  char* ws = nullptr;
+  if ((rc = mc_alloc(mc, ws, trace_ws_bytes(m, C)))) return fail(rc);
+  mc->trace_ws = ws;
+  Q.delta = d_delta;
+  Q.p_begin = d_begin;
+  Q.t_log = mc->t_log;
+  Q.t_sign = mc->t_sign;
+  std::vector<int64_t> begin(C);
+  for (int c = 0; c < C; ++c) begin[c] = int64_t(c) * NM;
+  if (hipMemcpy(d_delta, table, sizeof(double) * (p->n_delta + 1), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(d_begin, begin.data(), sizeof(int64_t) * C, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemset(mc->err, 0, sizeof(int32_t)) != hipSuccess)
+    return fail(set_error(HYB_E_HIP, "upload of the Monte Carlo tables failed"));
+  *out = mc;
+  // every chain starts empty (weight Tr_R of the empty configuration > 0)
+  std::vector<int32_t> k0(size_t(C) * F, 0);
+  std::vector<double> z(size_t(C) * F * KM, 0.0);
+  rc = hyb_mc_set_configs(mc, k0.data(), z.data(), z.data(), nullptr);
+  if (rc) {
+    hyb_mc_destroy(mc);
+    *out = nullptr;
+  }
+  return rc;
+}
+
+int hyb_mc_set_configs(hyb_mc* mc, const int32_t* k, const double* cre, const double* ann, void* stream) {
+  if (!mc || !k || !cre || !ann) return set_error(HYB_E_ARG, "NULL argument");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const int C = mc->p.n_chains, F = mc->F, KM = mc->p.kmax, NM = mc->p.nmax_ops;
+  const double beta = mc->p.beta;
+  std::vector<double> Mh(size_t(C) * F * KM * KM, 0.0), ptau(size_t(C) * NM, 0.0);
+  std::vector<int16_t> pfl(size_t(C) * NM, 0);
+  std::vector<int8_t> pdg(size_t(C) * NM, 0);
+  std::vector<int64_t> pend(C);
+  std::vector<int32_t> n_ops(C), signdet(C), sperm(C);
+  std::vector<double> logdet(C);
+  for (int c = 0; c < C; ++c) {
+    struct Op {
+      double t;
+      int f, dg;
+    };
+    std::vector<Op> ops;
+    std::vector<double> canon;
+    double ld = 0.0;
+    int sd = 1;
+    for (int f = 0; f < F; ++f) {
+      const int kf = k[c * F + f];
+      if (kf < 0 || kf > KM) return set_error(HYB_E_ARG, "chain %d flavor %d: order %d outside 0..%d", c, f, kf, KM);
+      const double* cf = cre + (size_t(c) * F + f) * KM;
+      const double* af = ann + (size_t(c) * F + f) * KM;
+      for (int i = 0; i < kf; ++i) {
+        if (!(cf[i] >= 0.0 && cf[i] < beta && af[i] >= 0.0 && af[i] < beta))
+          return set_error(HYB_E_UNSORTED, "chain %d: operator time outside [0, beta)", c);
+        ops.push_back({cf[i], f, 1});
+        ops.push_back({af[i], f, 0});
+        canon.push_back(af[i]);
+        canon.push_back(cf[i]);
+      }
+      if (kf > 0) {
+        std::vector<double> A(size_t(kf) * kf);
+        for (int i = 0; i < kf; ++i)
+          for (int j = 0; j < kf; ++j) A[i * kf + j] = delta_host(mc, cf[i] - af[j]);
+        // M = A^{-1}: rows of M follow annihilator labels, columns creator labels
+        double l = 0.0;
+        int sg = 1;
+        if (!lu_inverse(kf, A, Mh.data() + (size_t(c) * F + f) * KM * KM, KM, l, sg))
+          return set_error(HYB_E_ARG, "chain %d flavor %d: singular hybridization matrix", c, f);
+        ld += l;
+        sd *= sg;
+      }
+    }
+    if (int(ops.size()) > NM) return set_error(HYB_E_ARG, "chain %d: %zu operators exceed nmax_ops", c, ops.size());
+    std::sort(ops.begin(), ops.end(), [](const Op& a, const Op& b) { return a.t < b.t; });
+    for (size_t q = 1; q < ops.size(); ++q)
+      if (!(ops[q].t > ops[q - 1].t)) return set_error(HYB_E_UNSORTED, "chain %d: equal operator times", c);
+    for (size_t q = 0; q < ops.size(); ++q) {
+      ptau[size_t(c) * NM + q] = ops[q].t;
+      pfl[size_t(c) * NM + q] = int16_t(ops[q].f);
+      pdg[size_t(c) * NM + q] = int8_t(ops[q].dg);
+    }
+    int64_t inv = 0;
+    for (size_t a = 0; a < canon.size(); ++a)
+      for (size_t b = a + 1; b < canon.size(); ++b) inv += canon[a] < canon[b];
+    n_ops[c] = int(ops.size());
+    pend[c] = int64_t(c) * NM + int64_t(ops.size());
+    logdet[c] = ld;
+    signdet[c] = sd;
+    sperm[c] = (inv & 1) ? -1 : 1;
+  }
+  MCParams& Q = mc->Q;
+  const size_t nst = size_t(C) * ST_N;
+  std::vector<int64_t> zeros64(std::max(nst, size_t(C)), 0);
+  std::vector<double> zerosd(std::max(size_t(C), size_t(C) * F * mc->p.n_tau), 0.0);
+  MC_HIP_TRY(hipMemcpyAsync(Q.kf, k, sizeof(int32_t) * C * F, hipMemcpyHostToDevice, s));
+  MC_HIP_TRY(hipMemcpyAsync(Q.cre, cre, sizeof(double) * C * F * KM, hipMemcpyHostToDevice, s));
+  MC_HIP_TRY(hipMemcpyAsync(Q.ann, ann, sizeof(double) * C * F * KM, hipMemcpyHostToDevice, s));
+  MC_HIP_TRY(hipMemcpyAsync(Q.M, Mh.data(), sizeof(double) * Mh.size(), hipMemcpyHostToDevice, s));
+  MC_HIP_TRY(hipMemcpyAsync(Q.cur_n, n_ops.data(), sizeof(int32_t) * C, hipMemcpyHostToDevice, s));
+  MC_HIP_TRY(hipMemcpyAsync(Q.cur_tau, ptau.data(), sizeof(double) * ptau.size(), hipMemcpyHostToDevice, s));
+  MC_HIP_TRY(hipMemcpyAsync(Q.cur_fl, pfl.data(), sizeof(int16_t) * pfl.size(), hipMemcpyHostToDevice, s));
+  MC_HIP_TRY(hipMemcpyAsync(Q.cur_dg, pdg.data(), sizeof(int8_t) * pdg.size(), hipMemcpyHostToDevice, s));
+  MC_HIP_TRY(hipMemcpyAsync(Q.p_tau, ptau.data(), sizeof(double) * ptau.size(), hipMemcpyHostToDevice, s));
+  MC_HIP_TRY(hipMemcpyAsync(Q.p_fl, pfl.data(), sizeof(int16_t) * pfl.size(), hipMemcpyHostToDevice, s));
+  MC_HIP_TRY(hipMemcpyAsync(Q.p_dg, pdg.data(), sizeof(int8_t) * pdg.size(), hipMemcpyHostToDevice, s));
+  MC_HIP_TRY(hipMemcpyAsync(Q.p_end, pend.data(), sizeof(int64_t) * C, hipMemcpyHostToDevice, s));
+  MC_HIP_TRY(hipMemcpyAsync(Q.cur_logdet, logdet.data(), sizeof(double) * C, hipMemcpyHostToDevice, s));
+  MC_HIP_TRY(hipMemcpyAsync(Q.cur_signdet, signdet.data(), sizeof(int32_t) * C, hipMemcpyHostToDevice, s));
+  MC_HIP_TRY(hipMemcpyAsync(Q.stats, zeros64.data(), sizeof(int64_t) * nst, hipMemcpyHostToDevice, s));
+  MC_HIP_TRY(hipMemcpyAsync(Q.sign_sum, zerosd.data(), sizeof(double) * C, hipMemcpyHostToDevice, s));
+  MC_HIP_TRY(hipMemcpyAsync(Q.gacc, zerosd.data(), sizeof(double) * C * F * mc->p.n_tau, hipMemcpyHostToDevice, s));
+  MC_HIP_TRY(hipMemcpyAsync(Q.meas_sign, zerosd.data(), sizeof(double) * C, hipMemcpyHostToDevice, s));
+  MC_HIP_TRY(hipMemcpyAsync(Q.n_meas, zeros64.data(), sizeof(int64_t) * C, hipMemcpyHostToDevice, s));
+  // traces of the initial configurations (through the proposal slots)
+  int rc = run_traces(mc, s);
+  if (rc) return rc;
+  std::vector<double> tl(C);
+  std::vector<int8_t> ts(C);
+  int32_t err = 0;
+  MC_HIP_TRY(hipMemcpyAsync(tl.data(), mc->t_log, sizeof(double) * C, hipMemcpyDeviceToHost, s));
+  MC_HIP_TRY(hipMemcpyAsync(ts.data(), mc->t_sign, sizeof(int8_t) * C, hipMemcpyDeviceToHost, s));
+  MC_HIP_TRY(hipMemcpyAsync(&err, mc->err, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  MC_HIP_TRY(hipStreamSynchronize(s));
+  if (err) return set_error(HYB_E_NOCONV, "trace of the initial configurations failed (error bits %d)", err);
+  std::vector<int32_t> signtr(C), sign(C);
+  for (int c = 0; c < C; ++c) {
+    if (ts[c] == 0) return set_error(HYB_E_ARG, "chain %d: initial configuration has zero weight", c);
+    signtr[c] = ts[c];
+    sign[c] = sperm[c] * signtr[c] * signdet[c];
+  }
+  MC_HIP_TRY(hipMemcpyAsync(Q.cur_logtr, tl.data(), sizeof(double) * C, hipMemcpyHostToDevice, s));
+  MC_HIP_TRY(hipMemcpyAsync(Q.cur_signtr, signtr.data(), sizeof(int32_t) * C, hipMemcpyHostToDevice, s));
+  MC_HIP_TRY(hipMemcpyAsync(Q.cur_sign, sign.data(), sizeof(int32_t) * C, hipMemcpyHostToDevice, s));
+  MC_HIP_TRY(hipStreamSynchronize(s));
+  mc->step = 0;
+  return HYB_OK;
+}
+
+int hyb_mc_sweep(hyb_mc* mc, int32_t n_sweeps, void* stream) {
+  if (!mc) return set_error(HYB_E_ARG, "NULL argument");
+  if (n_sweeps < 0) return set_error(HYB_E_ARG, "negative sweep count");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const int C = mc->p.n_chains;
+  const size_t smem = sizeof(double) * std::max(mc->p.nmax_ops, 64);
+  const int64_t moves = int64_t(n_sweeps) * mc->p.moves_per_sweep;
+  for (int64_t mv = 0; mv < moves; ++mv) {
+    const int64_t step = mc->step;
+    k_mc_propose<<<C, 64, 0, s>>>(mc->Q, step);
+    int rc = run_traces(mc, s);
+    if (rc) return rc;
+    const int measure = ((step + 1) % mc->p.meas_every) == 0;
+    k_mc_accept<<<C, 64, smem, s>>>(mc->Q, step, measure);
+    MC_HIP_TRY(hipGetLastError());
+    mc->step = step + 1;
+  }
+  int32_t err = 0;
+  MC_HIP_TRY(hipMemcpyAsync(&err, mc->err, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  MC_HIP_TRY(hipStreamSynchronize(s));
+  if (err & ERR_NOCONV) return set_error(HYB_E_NOCONV, "Krylov propagation failed inside a move");
+  if (err & ERR_NONFINITE) return set_error(HYB_E_NONFINITE, "non-finite value inside a move");
+  if (err) return set_error(HYB_E_HIP, "inconsistent proposal (error bits %d)", err);
+  return HYB_OK;
+}
+
+int hyb_mc_get_state(const hyb_mc* mc, int32_t* k, double* cre, double* ann, double* M, double* logw, int8_t* sign,
+                     void* stream) {
+  if (!mc) return set_error(HYB_E_ARG, "NULL argument");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const int C = mc->p.n_chains, F = mc->F, KM = mc->p.kmax;
+  const MCParams& Q = mc->Q;
+  if (k) MC_HIP_TRY(hipMemcpyAsync(k, Q.kf, sizeof(int32_t) * C * F, hipMemcpyDeviceToHost, s));
+  if (cre) MC_HIP_TRY(hipMemcpyAsync(cre, Q.cre, sizeof(double) * C * F * KM, hipMemcpyDeviceToHost, s));
+  if (ann) MC_HIP_TRY(hipMemcpyAsync(ann, Q.ann, sizeof(double) * C * F * KM, hipMemcpyDeviceToHost, s));
+  if (M) MC_HIP_TRY(hipMemcpyAsync(M, Q.M, sizeof(double) * size_t(C) * F * KM * KM, hipMemcpyDeviceToHost, s));
+  std::vector<double> lt(C), ld(C);
+  std::vector<int32_t> sg(C);
+  MC_HIP_TRY(hipMemcpyAsync(lt.data(), Q.cur_logtr, sizeof(double) * C, hipMemcpyDeviceToHost, s));
+  MC_HIP_TRY(hipMemcpyAsync(ld.data(), Q.cur_logdet, sizeof(double) * C, hipMemcpyDeviceToHost, s));
+  MC_HIP_TRY(hipMemcpyAsync(sg.data(), Q.cur_sign, sizeof(int32_t) * C, hipMemcpyDeviceToHost, s));
+  MC_HIP_TRY(hipStreamSynchronize(s));
+  for (int c = 0; c < C; ++c) {
+    if (logw) logw[c] = lt[c] + ld[c];
+    if (sign) sign[c] = int8_t(sg[c]);
+  }
+  return HYB_OK;
+}
+
+int hyb_mc_get_stats(const hyb_mc* mc, hyb_mc_stats* out, void* stream) {
+  if (!mc || !out) return set_error(HYB_E_ARG, "NULL argument");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const int C = mc->p.n_chains;
+  std::vector<int64_t> st(size_t(C) * ST_N);
+  std::vector<double> ss(C);
+  MC_HIP_TRY(hipMemcpyAsync(st.data(), mc->Q.stats, sizeof(int64_t) * st.size(), hipMemcpyDeviceToHost, s));
+  MC_HIP_TRY(hipMemcpyAsync(ss.data(), mc->Q.sign_sum, sizeof(double) * C, hipMemcpyDeviceToHost, s));
+  MC_HIP_TRY(hipStreamSynchronize(s));
+  *out = hyb_mc_stats{};
+  for (int c = 0; c < C; ++c) {
+    const int64_t* a = st.data() + size_t(c) * ST_N;
+    out->insert_proposed += a[ST_INS_PROP];
+    out->insert_accepted += a[ST_INS_ACC];
+    out->remove_proposed += a[ST_REM_PROP];
+    out->remove_accepted += a[ST_REM_ACC];
+    out->impossible += a[ST_IMPOSSIBLE];
+    out->zero_weight += a[ST_ZERO];
+    out->order_sum += double(a[ST_ORDER]);
+    out->moves += a[ST_MOVES];
+    out->sign_sum += ss[c];
+  }
+  return HYB_OK;
+}
+
+int hyb_mc_get_accumulators(const hyb_mc* mc, double* gacc, double* meas_sign, int64_t* n_meas, void* stream) {
+  if (!mc) return set_error(HYB_E_ARG, "NULL argument");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const int C = mc->p.n_chains, F = mc->F;
+  if (gacc)
+    MC_HIP_TRY(hipMemcpyAsync(gacc, mc->Q.gacc, sizeof(double) * size_t(C) * F * mc->p.n_tau, hipMemcpyDeviceToHost, s));
+  if (meas_sign) MC_HIP_TRY(hipMemcpyAsync(meas_sign, mc->Q.meas_sign, sizeof(double) * C, hipMemcpyDeviceToHost, s));
+  if (n_meas) MC_HIP_TRY(hipMemcpyAsync(n_meas, mc->Q.n_meas, sizeof(int64_t) * C, hipMemcpyDeviceToHost, s));
+  MC_HIP_TRY(hipStreamSynchronize(s));
+  return HYB_OK;
+}
+
+int hyb_mc_measure(const hyb_mc* mc, double* G, double* sign_avg, void* stream) {
+  if (!mc || !G) return set_error(HYB_E_ARG, "NULL argument");
+  const int C = mc->p.n_chains, F = mc->F, NT = mc->p.n_tau;
+  std::vector<double> acc(size_t(C) * F * NT), ms(C);
+  std::vector<int64_t> nm(C);
+  int rc = hyb_mc_get_accumulators(mc, acc.data(), ms.data(), nm.data(), stream);
+  if (rc) return rc;
+  double ssum = 0.0;
+  int64_t ntot = 0;
+  for (int c = 0; c < C; ++c) {
+    ssum += ms[c];
+    ntot += nm[c];
+  }
+  if (ntot == 0 || ssum == 0.0) return set_error(HYB_E_STATE, "no measurements (or zero average sign)");
+  const double h = mc->p.beta / NT;
+  for (int f = 0; f < F; ++f)
+    for (int b = 0; b < NT; ++b) {
+      double a = 0.0;
+      for (int c = 0; c < C; ++c) a += acc[(size_t(c) * F + f) * NT + b];
+      G[f * NT + b] = -a / (mc->p.beta * h * ssum);
+    }
+  if (sign_avg) *sign_avg = ssum / double(ntot);
+  return HYB_OK;
+}
+
+int hyb_mc_reset_measurements(hyb_mc* mc, void* stream) {
+  if (!mc) return set_error(HYB_E_ARG, "NULL argument");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const int C = mc->p.n_chains, F = mc->F;
+  MC_HIP_TRY(hipMemsetAsync(mc->Q.gacc, 0, sizeof(double) * size_t(C) * F * mc->p.n_tau, s));
+  MC_HIP_TRY(hipMemsetAsync(mc->Q.meas_sign, 0, sizeof(double) * C, s));
+  MC_HIP_TRY(hipMemsetAsync(mc->Q.n_meas, 0, sizeof(int64_t) * C, s));
+  MC_HIP_TRY(hipMemsetAsync(mc->Q.stats, 0, sizeof(int64_t) * size_t(C) * ST_N, s));
+  MC_HIP_TRY(hipMemsetAsync(mc->Q.sign_sum, 0, sizeof(double) * C, s));
+  MC_HIP_TRY(hipStreamSynchronize(s));
+  return HYB_OK;
+}
+
+int hyb_mc_step_count(const hyb_mc* mc, int64_t* step) {
+  if (!mc || !step) return set_error(HYB_E_ARG, "NULL argument");
+  *step = mc->step;
+  return HYB_OK;
+}
+
+}  // extern "C"

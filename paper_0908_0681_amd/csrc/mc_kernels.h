@@ -1,0 +1,400 @@
+// Device side of the Monte Carlo layer (included by mc.hip and by CPU builds of
+// the same code): move records, the counter-based generator, the bath
+// interpolation, and the bodies of the proposal and acceptance kernels.  One
+// wavefront (64 lanes) per chain.
+#pragma once
+
+#include "trace_kernels.h"
+
+// Operator times, table positions and acceptance ratios are computed with one
+// rounding per operation (no fused multiply-add), so that they are the same
+// doubles on every platform that follows IEEE 754.  The pragma covers this
+// file; the library builds the including translation unit with
+// -ffp-contract=off so that inlined helpers from other headers are covered too.
+#ifdef __clang__
+#pragma clang fp contract(off)
+#endif
+
+namespace hyb {
+
+struct MoveRec {
+  int32_t kind;   // 0 impossible, 1 insert, 2 remove
+  int32_t valid;  // 0: the proposed configuration has zero weight (time tie)
+  int32_t f, k, i, j;
+  int32_t pad;
+  double ts, te;  // insert: creator / annihilator times
+  double ratio;   // det A_f' / det A_f (with the relabelling of a removal)
+};
+
+enum : int { ST_INS_PROP = 0, ST_INS_ACC, ST_REM_PROP, ST_REM_ACC, ST_IMPOSSIBLE, ST_ZERO, ST_ORDER, ST_MOVES, ST_N };
+
+struct MCParams {
+  int32_t n_chains, F, kmax, nmax, n_delta, n_tau;
+  double beta;
+  uint32_t key0, key1;
+  const double* delta;
+  int32_t* kf;   // [C][F]
+  double* cre;   // [C][F][kmax]
+  double* ann;   // [C][F][kmax]
+  double* M;     // [C][F][kmax][kmax], row = annihilator label, column = creator label
+  int32_t* cur_n;
+  double* cur_tau;  // [C][nmax]
+  int16_t* cur_fl;
+  int8_t* cur_dg;
+  const int64_t* p_begin;  // [C] = c * nmax
+  int64_t* p_end;
+  double* p_tau;
+  int16_t* p_fl;
+  int8_t* p_dg;
+  MoveRec* mv;
+  double* uvec;  // [C][kmax]: M b of an insertion
+  double* vvec;  // [C][kmax]: c^T M of an insertion
+  double* cur_logtr;
+  int32_t* cur_signtr;
+  double* cur_logdet;
+  int32_t* cur_signdet;
+  int32_t* cur_sign;
+  const double* t_log;
+  const int8_t* t_sign;
+  int64_t* stats;     // [C][ST_N]
+  double* sign_sum;   // [C]
+  double* gacc;       // [C][F][n_tau]
+  double* meas_sign;  // [C]
+  int64_t* n_meas;    // [C]
+};
+
+// ---- generator -------------------------------------------------------------
+
+__device__ __forceinline__ void philox4x32_10(uint32_t (&c)[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint64_t p0 = uint64_t(0xD2511F53u) * c[0];
+    const uint64_t p1 = uint64_t(0xCD9E8D57u) * c[2];
+    const uint32_t n0 = uint32_t(p1 >> 32) ^ c[1] ^ k0;
+    const uint32_t n2 = uint32_t(p0 >> 32) ^ c[3] ^ k1;
+    c[0] = n0;
+    c[1] = uint32_t(p1);
+    c[2] = n2;
+    c[3] = uint32_t(p0);
+  }
+}
+
+// 53 random bits from two words; exact in double, identical on every platform.
+__device__ __forceinline__ double u01(uint32_t a, uint32_t b) {
+  return (double(a >> 5) * 67108864.0 + double(b >> 6)) * (1.0 / 9007199254740992.0);
+}
+
+__device__ inline void move_uniforms(const MCParams& Q, int chain, int64_t step, double (&u)[6]) {
+#pragma unroll
+  for (int call = 0; call < 3; ++call) {
+    uint32_t c[4] = {uint32_t(uint64_t(step)), uint32_t(uint64_t(step) >> 32), uint32_t(chain), uint32_t(call)};
+    philox4x32_10(c, Q.key0, Q.key1);
+    u[2 * call] = u01(c[0], c[1]);
+    u[2 * call + 1] = u01(c[2], c[3]);
+  }
+}
+
+// ---- bath --------------------------------------------------------------------
+
+// Linear interpolation of the tabulated Delta on [0, beta], antiperiodic outside.
+__device__ __forceinline__ double delta_at(const MCParams& Q, double tau) {
+  double sgn = 1.0;
+  if (tau < 0.0) {
+    tau = __dadd_rn(tau, Q.beta);
+    sgn = -1.0;
+  }
+  const double x = __dmul_rn(__ddiv_rn(tau, Q.beta), double(Q.n_delta));
+  int k = int(x);
+  if (k > Q.n_delta - 1) k = Q.n_delta - 1;
+  const double fr = __dadd_rn(x, -double(k));
+  const double a = Q.delta[k], b = Q.delta[k + 1];
+  return sgn * __dadd_rn(a, __dmul_rn(fr, __dadd_rn(b, -a)));
+}
+
+__device__ __forceinline__ double wave_sum64(double x) { return wave_sum(x); }
+
+// ---- proposal ---------------------------------------------------------------------
+
+// One workgroup (one wavefront) per chain: draws the move, computes the
+// determinant ratio (and, for an insertion, M b and c^T M for the update) and
+// writes the proposed time-ordered operator list into the chain's trace slot.
+__device__ inline void mc_propose(const MCParams& Q, int c, int64_t step, double* sb, double* sc) {
+  const int lane = threadIdx.x;
+  double u[6];
+  move_uniforms(Q, c, step, u);
+  const int F = Q.F, KM = Q.kmax, NM = Q.nmax;
+  int f = int(__dmul_rn(u[0], double(F)));
+  if (f > F - 1) f = F - 1;
+  const bool ins = u[1] < 0.5;
+  const int k = Q.kf[c * F + f];
+  const int n = Q.cur_n[c];
+  const double* cre_f = Q.cre + (int64_t(c) * F + f) * KM;
+  const double* ann_f = Q.ann + (int64_t(c) * F + f) * KM;
+  const double* Mf = Q.M + (int64_t(c) * F + f) * KM * KM;
+  const double* otau = Q.cur_tau + int64_t(c) * NM;
+  const int16_t* ofl = Q.cur_fl + int64_t(c) * NM;
+  const int8_t* odg = Q.cur_dg + int64_t(c) * NM;
+  double* ntau = Q.p_tau + int64_t(c) * NM;
+  int16_t* nfl = Q.p_fl + int64_t(c) * NM;
+  int8_t* ndg = Q.p_dg + int64_t(c) * NM;
+  MoveRec rec{};
+  rec.f = f;
+  rec.k = k;
+  int n_new = 0;
+  if (ins) {
+    rec.kind = 1;
+    if (k >= KM || n + 2 > NM) {
+      rec.kind = 0;
+    } else {
+      const double ts = __dmul_rn(u[2], Q.beta);
+      double te = __dadd_rn(ts, __dmul_rn(u[3], Q.beta));
+      if (te >= Q.beta) te = __dadd_rn(te, -Q.beta);
+      rec.ts = ts;
+      rec.te = te;
+      double cs = 0.0, ce = 0.0, tie = (ts == te) ? 1.0 : 0.0;
+      for (int p = lane; p < n; p += 64) {
+        const double t = otau[p];
+        cs += (t < ts) ? 1.0 : 0.0;
+        ce += (t < te) ? 1.0 : 0.0;
+        if (t == ts || t == te) tie = 1.0;
+      }
+      cs = wave_sum64(cs);
+      ce = wave_sum64(ce);
+      tie = wave_sum64(tie);
+      rec.valid = tie == 0.0;
+      if (rec.valid) {
+        for (int p = lane; p < n; p += 64) {
+          const double t = otau[p];
+          const int np = p + (ts < t ? 1 : 0) + (te < t ? 1 : 0);
+          ntau[np] = t;
+          nfl[np] = ofl[p];
+          ndg[np] = odg[p];
+        }
+        if (lane == 0) {
+          const int ps = int(cs) + (te < ts ? 1 : 0);
+          const int pe = int(ce) + (ts < te ? 1 : 0);
+          ntau[ps] = ts;
+          nfl[ps] = int16_t(f);
+          ndg[ps] = 1;
+          ntau[pe] = te;
+          nfl[pe] = int16_t(f);
+          ndg[pe] = 0;
+        }
+        n_new = n + 2;
+        // A' = [[A, b], [c^T, d]]: b_r = Delta(tau'_r - te), c_r = Delta(ts - tau_r)
+        if (lane < k) {
+          sb[lane] = delta_at(Q, __dadd_rn(cre_f[lane], -te));
+          sc[lane] = delta_at(Q, __dadd_rn(ts, -ann_f[lane]));
+        }
+        __syncthreads();
+        double dot = 0.0;
+        if (lane < k) {
+          double ur = 0.0, vr = 0.0;
+          for (int q = 0; q < k; ++q) {
+            ur += Mf[lane * KM + q] * sb[q];   // (M b)_lane
+            vr += sc[q] * Mf[q * KM + lane];   // (c^T M)_lane
+          }
+          Q.uvec[int64_t(c) * KM + lane] = ur;
+          Q.vvec[int64_t(c) * KM + lane] = vr;
+          dot = sc[lane] * ur;
+        }
+        dot = wave_sum64(dot);
+        rec.ratio = delta_at(Q, __dadd_rn(ts, -te)) - dot;
+      }
+    }
+  } else {
+    rec.kind = 2;
+    if (k == 0) {
+      rec.kind = 0;
+    } else {
+      int i = int(__dmul_rn(u[2], double(k)));
+      int j = int(__dmul_rn(u[3], double(k)));
+      if (i > k - 1) i = k - 1;
+      if (j > k - 1) j = k - 1;
+      rec.i = i;
+      rec.j = j;
+      rec.valid = 1;
+      // det of A without row i and column j, after moving the last labels into the holes
+      const double s_i = (i != k - 1) ? -1.0 : 1.0, s_j = (j != k - 1) ? -1.0 : 1.0;
+      rec.ratio = s_i * s_j * Mf[j * KM + i];
+      const double tc = cre_f[i], ta = ann_f[j];
+      double pc = 0.0, pa = 0.0;
+      for (int p = lane; p < n; p += 64) {
+        if (otau[p] == tc && ofl[p] == f && odg[p] == 1) pc = double(p);
+        if (otau[p] == ta && ofl[p] == f && odg[p] == 0) pa = double(p);
+      }
+      const int pos_c = int(wave_sum64(pc)), pos_a = int(wave_sum64(pa));
+      for (int p = lane; p < n; p += 64) {
+        if (p == pos_c || p == pos_a) continue;
+        const int np = p - (p > pos_c ? 1 : 0) - (p > pos_a ? 1 : 0);
+        ntau[np] = otau[p];
+        nfl[np] = ofl[p];
+        ndg[np] = odg[p];
+      }
+      n_new = n - 2;
+    }
+  }
+  if (lane == 0) {
+    Q.mv[c] = rec;
+    Q.p_end[c] = Q.p_begin[c] + ((rec.kind != 0 && rec.valid) ? n_new : 0);
+  }
+}
+
+// ---- acceptance, update, measurement ------------------------------------------
+
+// Sign of the permutation from the canonical string to descending time order,
+// counted over the chain's current per-flavor lists (all 64 lanes take part).
+__device__ int perm_sign(const MCParams& Q, int c, double* canon) {
+  const int F = Q.F, KM = Q.kmax;
+  int n = 0;
+  for (int g = 0; g < F; ++g) {
+    const int kg = Q.kf[c * F + g];
+    const double* cg = Q.cre + (int64_t(c) * F + g) * KM;
+    const double* ag = Q.ann + (int64_t(c) * F + g) * KM;
+    for (int i = threadIdx.x; i < kg; i += 64) {
+      canon[n + 2 * i] = ag[i];
+      canon[n + 2 * i + 1] = cg[i];
+    }
+    n += 2 * kg;
+  }
+  __syncthreads();
+  double inv = 0.0;
+  for (int p = threadIdx.x; p < n; p += 64) {
+    const double tp = canon[p];
+    int cnt = 0;
+    for (int q = p + 1; q < n; ++q) cnt += (tp < canon[q]) ? 1 : 0;
+    inv += double(cnt);
+  }
+  inv = wave_sum64(inv);
+  __syncthreads();
+  return (int64_t(inv) & 1) ? -1 : 1;
+}
+
+// canon: LDS scratch of max(nmax, 64) doubles (its head doubles as a row buffer)
+__device__ inline void mc_accept(const MCParams& Q, int c, int64_t step, int measure, double* canon) {
+  const int lane = threadIdx.x;
+  const int F = Q.F, KM = Q.kmax, NM = Q.nmax;
+  double u[6];
+  move_uniforms(Q, c, step, u);
+  const MoveRec rec = Q.mv[c];
+  const int f = rec.f, k = rec.k;
+  int64_t* st = Q.stats + int64_t(c) * ST_N;
+  bool accept = false;
+  if (rec.kind != 0 && rec.valid && Q.t_sign[c] != 0 && rec.ratio != 0.0) {
+    const double log_factor = (rec.kind == 1) ? 2.0 * (log(Q.beta) - log(double(k + 1)))
+                                              : 2.0 * (log(double(k)) - log(Q.beta));
+    const double log_ratio = (Q.t_log[c] - Q.cur_logtr[c]) + log(fabs(rec.ratio)) + log_factor;
+    accept = u[4] < exp(log_ratio);
+  }
+  if (lane == 0) {
+    if (rec.kind == 0) st[ST_IMPOSSIBLE] += 1;
+    if (rec.kind == 1) st[ST_INS_PROP] += 1;
+    if (rec.kind == 2) st[ST_REM_PROP] += 1;
+    if (rec.kind != 0 && (!rec.valid || Q.t_sign[c] == 0 || rec.ratio == 0.0)) st[ST_ZERO] += 1;
+    if (accept) st[rec.kind == 1 ? ST_INS_ACC : ST_REM_ACC] += 1;
+  }
+  if (accept) {
+    double* Mf = Q.M + (int64_t(c) * F + f) * KM * KM;
+    double* cre_f = Q.cre + (int64_t(c) * F + f) * KM;
+    double* ann_f = Q.ann + (int64_t(c) * F + f) * KM;
+    const double r = rec.ratio;
+    if (rec.kind == 1) {
+      // M' = [[M + u v^T / r, -u / r], [-v^T / r, 1 / r]]
+      const double* uv = Q.uvec + int64_t(c) * KM;
+      const double* vv = Q.vvec + int64_t(c) * KM;
+      if (lane < k) {
+        const double ur = uv[lane];
+        for (int q = 0; q < k; ++q) Mf[lane * KM + q] += ur * vv[q] / r;
+        Mf[lane * KM + k] = -ur / r;
+      } else if (lane == k) {
+        for (int q = 0; q < k; ++q) Mf[k * KM + q] = -vv[q] / r;
+        Mf[k * KM + k] = 1.0 / r;
+      }
+      if (lane == 0) {
+        cre_f[k] = rec.ts;
+        ann_f[k] = rec.te;
+        Q.kf[c * F + f] = k + 1;
+      }
+    } else {
+      // swap row j <-> k-1 and column i <-> k-1 of M, then drop the last row and
+      // column: M'[r][s] = M''[r][s] - M''[r][k-1] M''[k-1][s] / M''[k-1][k-1]
+      const int i = rec.i, j = rec.j;
+      double* rowj = canon;  // old row j of M
+      for (int q = lane; q < k; q += 64) rowj[q] = Mf[j * KM + q];
+      __syncthreads();
+      const double mji = rowj[i];
+      if (lane < k - 1) {
+        const int src = (lane == j) ? k - 1 : lane;
+        const double m_ri = Mf[src * KM + i];
+        for (int q = 0; q < k - 1; ++q) {
+          const int qs = (q == i) ? k - 1 : q;
+          Mf[lane * KM + q] = Mf[src * KM + qs] - m_ri * rowj[qs] / mji;
+        }
+      }
+      __syncthreads();
+      if (lane == 0) {
+        cre_f[i] = cre_f[k - 1];
+        ann_f[j] = ann_f[k - 1];
+        Q.kf[c * F + f] = k - 1;
+      }
+    }
+    // the proposed operator list becomes the current one
+    const int n_new = int(Q.p_end[c] - Q.p_begin[c]);
+    for (int p = lane; p < n_new; p += 64) {
+      Q.cur_tau[int64_t(c) * NM + p] = Q.p_tau[int64_t(c) * NM + p];
+      Q.cur_fl[int64_t(c) * NM + p] = Q.p_fl[int64_t(c) * NM + p];
+      Q.cur_dg[int64_t(c) * NM + p] = Q.p_dg[int64_t(c) * NM + p];
+    }
+    __syncthreads();
+    const int sp = perm_sign(Q, c, canon);
+    if (lane == 0) {
+      Q.cur_n[c] = n_new;
+      Q.cur_logtr[c] = Q.t_log[c];
+      Q.cur_signtr[c] = Q.t_sign[c];
+      Q.cur_logdet[c] += log(fabs(r));
+      Q.cur_signdet[c] *= (r > 0.0) ? 1 : -1;
+      Q.cur_sign[c] = sp * Q.cur_signtr[c] * Q.cur_signdet[c];
+    }
+  }
+  __syncthreads();
+  const double sgn = double(Q.cur_sign[c]);
+  if (lane == 0) {
+    int64_t order = 0;
+    for (int g = 0; g < F; ++g) order += Q.kf[c * F + g];
+    st[ST_ORDER] += order;
+    st[ST_MOVES] += 1;
+    Q.sign_sum[c] += sgn;
+  }
+  if (measure) {
+    // G_f(tau) += sign * sum_ij M[j][i] delta~(tau, tau_j - tau'_i), binned
+    for (int g = 0; g < F; ++g) {
+      const int kg = Q.kf[c * F + g];
+      const double* cg = Q.cre + (int64_t(c) * F + g) * KM;
+      const double* ag = Q.ann + (int64_t(c) * F + g) * KM;
+      const double* Mg = Q.M + (int64_t(c) * F + g) * KM * KM;
+      double* acc = Q.gacc + (int64_t(c) * F + g) * Q.n_tau;
+      for (int e = lane; e < kg * kg; e += 64) {
+        const int i = e / kg, j = e - i * kg;
+        double d = __dadd_rn(ag[j], -cg[i]);
+        double s = 1.0;
+        if (d < 0.0) {
+          d = __dadd_rn(d, Q.beta);
+          s = -1.0;
+        }
+        int b = int(__dmul_rn(__ddiv_rn(d, Q.beta), double(Q.n_tau)));
+        if (b > Q.n_tau - 1) b = Q.n_tau - 1;
+        atomicAdd(&acc[b], sgn * s * Mg[j * KM + i]);
+      }
+    }
+    if (lane == 0) {
+      Q.meas_sign[c] += sgn;
+      Q.n_meas[c] += 1;
+    }
+  }
+}
+
+}  // namespace hyb

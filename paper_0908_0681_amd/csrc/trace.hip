@@ -9,6 +9,7 @@
 
 #include "hyb_internal.h"
 #include "trace_kernels.h"
+#include "trace_launch.h"
 
 namespace hyb {
 
@@ -34,18 +35,21 @@ __global__ void k_scan(TraceParams P) {
 
 template <typename VT, int NT>
 __global__ __launch_bounds__(NT) void k_path_init(TraceParams P) {
+  if (int(blockIdx.x) >= P.counters[0]) return;  // grids may be sized for every pair
   path_init<VT, NT>(P, blockIdx.x);
 }
 
 template <typename VT, int NT, int RPT>
 __global__ __launch_bounds__(NT) void k_path_op(TraceParams P, int k) {
   __shared__ double red[NT / 64];
+  if (int(blockIdx.x) >= P.counters[0]) return;
   path_op<VT, NT, RPT>(P, blockIdx.x, k, red);
 }
 
 template <typename VT, int NT, int RPT, int MAXM>
 __global__ __launch_bounds__(NT) void k_path_prop(TraceParams P, int k) {
   __shared__ typename PathEngine<VT, NT, RPT, MAXM>::Smem S;
+  if (int(blockIdx.x) >= P.counters[0]) return;
   path_prop<VT, NT, RPT, MAXM>(P, blockIdx.x, k, S);
 }
 
@@ -57,6 +61,13 @@ __global__ __launch_bounds__(NT) void k_path_chunk(TraceParams P, int k0, int k1
   __shared__ typename PathEngine<VT, NT, RPT, MAXM>::Smem S;
   __shared__ double red[NT / 64];
   const int w = blockIdx.x;
+  if (w >= P.counters[0]) return;
+  {
+    // stop at this path's own length (uniform over the workgroup)
+    const int c = P.work[w] / P.n_ret;
+    const int64_t n = cfg_end(P, c) - P.offsets[c];
+    if (int64_t(k1) > n) k1 = int(n);
+  }
   for (int k = k0; k < k1; ++k) {
     if (k > 0) {
       path_prop<VT, NT, RPT, MAXM>(P, w, k, S);
@@ -70,7 +81,12 @@ __global__ __launch_bounds__(NT) void k_path_chunk(TraceParams P, int k0, int k1
 template <typename VT, int NT, int RPT>
 __global__ __launch_bounds__(NT) void k_path_final(TraceParams P) {
   __shared__ double red[NT / 64];
+  if (int(blockIdx.x) >= P.counters[0]) return;
   path_final<VT, NT, RPT>(P, blockIdx.x, red);
+}
+
+__global__ void k_fold_errors(const int32_t* counters, int32_t* acc) {
+  if (threadIdx.x == 0 && counters[2] != 0) atomicOr(acc, counters[2]);
 }
 
 __global__ void k_reduce(TraceParams P, double* out_log, int8_t* out_sign, int32_t* out_steps,
@@ -274,6 +290,100 @@ static int error_from_bits(int bits) {
   if (bits & ERR_FLAVOR) return set_error(HYB_E_FLAVOR, "flavor or dagger out of range");
   if (bits & ERR_NONFINITE) return set_error(HYB_E_NONFINITE, "non-finite value in the propagation");
   if (bits & ERR_NOCONV) return set_error(HYB_E_NOCONV, "Krylov propagation exceeded the substep limit");
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// device-resident launch (no host round trip)
+// ---------------------------------------------------------------------------
+
+namespace {
+struct ResidentLayout {
+  size_t cnt, work, psign, plog, psteps, psub, prs, prw, srs, srw, sblock, sstatus, ssteps, ssubs, sell, svec, total;
+};
+ResidentLayout resident_layout(const hyb_model* m, int nc, size_t vbytes) {
+  const int64_t npairs = int64_t(nc) * int64_t(m->ret_block.size());
+  const int vstride = (m->max_dim + 63) & ~63;
+  ResidentLayout L{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align_up(off + bytes);
+    return o;
+  };
+  L.cnt = take(4 * sizeof(int32_t));
+  L.work = take(npairs * sizeof(int32_t));
+  L.psign = take(npairs * sizeof(int8_t));
+  L.plog = take(npairs * sizeof(double));
+  L.psteps = take(npairs * sizeof(int32_t));
+  L.psub = take(npairs * sizeof(int32_t));
+  L.prs = take(npairs * sizeof(int64_t));
+  L.prw = take(npairs * sizeof(int64_t));
+  L.srs = take(npairs * sizeof(int64_t));
+  L.srw = take(npairs * sizeof(int64_t));
+  L.sblock = take(npairs * sizeof(int32_t));
+  L.sstatus = take(npairs * sizeof(int32_t));
+  L.ssteps = take(npairs * sizeof(int32_t));
+  L.ssubs = take(npairs * sizeof(int32_t));
+  L.sell = take(npairs * sizeof(double));
+  L.svec = take(2 * size_t(npairs) * vstride * vbytes);
+  L.total = off;
+  return L;
+}
+}  // namespace
+
+size_t trace_ws_bytes(const hyb_model* m, int n_configs) {
+  return resident_layout(m, n_configs, sizeof(double)).total;
+}
+
+int trace_resident(hyb_model* m, int nc, const int64_t* begin, const int64_t* ends, const double* tau,
+                   const int16_t* flavor, const int8_t* dagger, int max_ops, double beta, void* ws,
+                   double* out_log, int8_t* out_sign, int32_t* err_accum, hipStream_t s) {
+  const int vi = m->variant >= 0 ? m->variant : auto_variant(m);
+  const Variant& V = kVariants[vi];
+  const ResidentLayout L = resident_layout(m, nc, V.fp64 ? sizeof(double) : sizeof(float));
+  const int64_t npairs = int64_t(nc) * int64_t(m->ret_block.size());
+  char* w = static_cast<char*>(ws);
+  TraceParams P = base_params(m);
+  P.n_configs = nc;
+  P.n_pairs = int32_t(npairs);
+  P.beta = beta;
+  P.offsets = begin;
+  P.ends = ends;
+  P.tau = tau;
+  P.flavor = flavor;
+  P.dagger = dagger;
+  P.counters = reinterpret_cast<int32_t*>(w + L.cnt);
+  P.work = reinterpret_cast<int32_t*>(w + L.work);
+  P.p_sign = reinterpret_cast<int8_t*>(w + L.psign);
+  P.p_log = reinterpret_cast<double*>(w + L.plog);
+  P.p_steps = reinterpret_cast<int32_t*>(w + L.psteps);
+  P.p_sub = reinterpret_cast<int32_t*>(w + L.psub);
+  P.p_rowsteps = reinterpret_cast<int64_t*>(w + L.prs);
+  P.p_rows = reinterpret_cast<int64_t*>(w + L.prw);
+  P.st_rowsteps = reinterpret_cast<int64_t*>(w + L.srs);
+  P.st_rows = reinterpret_cast<int64_t*>(w + L.srw);
+  P.st_block = reinterpret_cast<int32_t*>(w + L.sblock);
+  P.st_status = reinterpret_cast<int32_t*>(w + L.sstatus);
+  P.st_steps = reinterpret_cast<int32_t*>(w + L.ssteps);
+  P.st_subs = reinterpret_cast<int32_t*>(w + L.ssubs);
+  P.st_ell = reinterpret_cast<double*>(w + L.sell);
+  P.st_vec = w + L.svec;
+  P.vstride = (m->max_dim + 63) & ~63;
+  k_init_counters<<<1, 64, 0, s>>>(P.counters);
+  const int scan_threads = 256;
+  k_scan<<<unsigned((npairs + scan_threads - 1) / scan_threads), scan_threads, 0, s>>>(P);
+  if (npairs > 0) {
+    int k0 = 0, k1 = max_ops;
+    void* a0[] = {&P};
+    void* ak[] = {&P, &k0, &k1};
+    HIP_TRY(hipLaunchKernel(V.init_fn, dim3(unsigned(npairs)), dim3(V.nt), a0, 0, s));
+    HIP_TRY(hipLaunchKernel(V.chunk_fn, dim3(unsigned(npairs)), dim3(V.nt), ak, 0, s));
+    HIP_TRY(hipLaunchKernel(V.final_fn, dim3(unsigned(npairs)), dim3(V.nt), a0, 0, s));
+  }
+  k_reduce<<<(nc + 255) / 256, 256, 0, s>>>(P, out_log, out_sign, nullptr, nullptr, nullptr, nullptr, nullptr);
+  k_fold_errors<<<1, 64, 0, s>>>(P.counters, err_accum);
+  HIP_TRY(hipGetLastError());
   return 0;
 }
 

@@ -45,6 +45,7 @@ struct TraceParams {
   // configurations
   int32_t n_configs;
   const int64_t* offsets;
+  const int64_t* ends;  // nullptr: ops of config c are [offsets[c], offsets[c+1]); else [offsets[c], ends[c])
   const double* tau;
   const int16_t* flavor;
   const int8_t* dagger;
@@ -76,6 +77,11 @@ struct TraceParams {
   int32_t vstride;     // elements per path vector (>= largest block)
   double zero_tol2;    // an operator leaving less than this squared norm ends the path
 };
+
+__device__ __forceinline__ int64_t cfg_end(const TraceParams& P, int c) {
+  return P.ends ? P.ends[c] : P.offsets[c + 1];
+}
+
 
 enum : int32_t { PATH_ACTIVE = 0, PATH_EMPTY = 1, PATH_ZERO = 2, PATH_FAILED = 3 };
 
@@ -552,7 +558,7 @@ struct PathEngine {
 
 __device__ inline void scan_pair(const TraceParams& P, int64_t id) {
   const int c = int(id / P.n_ret), r = int(id - int64_t(c) * P.n_ret);
-  const int64_t o0 = P.offsets[c], o1 = P.offsets[c + 1];
+  const int64_t o0 = P.offsets[c], o1 = cfg_end(P, c);
   int err = 0;
   const BlockDev B0 = P.blocks[P.ret_block[r]];
   int nu = B0.n_up, nd = B0.n_dn;
@@ -642,7 +648,7 @@ template <typename VT, int NT>
 __device__ inline void path_init(const TraceParams& P, int w) {
   const int id = P.work[w];
   const int c = id / P.n_ret, r = id - c * P.n_ret;
-  const int64_t o0 = P.offsets[c], o1 = P.offsets[c + 1];
+  const int64_t o0 = P.offsets[c], o1 = cfg_end(P, c);
   const int b = P.ret_block[r];
   const int dim = P.blocks[b].dim;
   const VT* src = (sizeof(VT) == 8) ? reinterpret_cast<const VT*>(P.ret_vec64 + P.ret_off[r])
@@ -668,7 +674,7 @@ __device__ inline void path_op(const TraceParams& P, int w, int k, double* red) 
   if (P.st_status[w] != PATH_ACTIVE) return;
   const int id = P.work[w];
   const int c = id / P.n_ret;
-  const int64_t o0 = P.offsets[c], o1 = P.offsets[c + 1];
+  const int64_t o0 = P.offsets[c], o1 = cfg_end(P, c);
   if (k >= o1 - o0) return;
   const int f = P.flavor[o0 + k];
   const int dg = P.dagger[o0 + k] ? 1 : 0;
@@ -738,7 +744,7 @@ __device__ inline void path_prop(const TraceParams& P, int w, int k, typename Pa
   if (P.st_status[w] != PATH_ACTIVE) return;
   const int id = P.work[w];
   const int c = id / P.n_ret;
-  const int64_t o0 = P.offsets[c], o1 = P.offsets[c + 1];
+  const int64_t o0 = P.offsets[c], o1 = cfg_end(P, c);
   if (k >= o1 - o0) return;
   E eng(P, S);
   const BlockDev B = P.blocks[P.st_block[w]];
@@ -787,7 +793,7 @@ __device__ inline void path_final(const TraceParams& P, int w, double* red) {
     }
     return;
   }
-  const int64_t nops = P.offsets[c + 1] - P.offsets[c];
+  const int64_t nops = cfg_end(P, c) - P.offsets[c];
   const int b = P.ret_block[r];
   const int dim = P.blocks[b].dim;
   const VT* v = path_vec<VT>(P, int(nops & 1), w);

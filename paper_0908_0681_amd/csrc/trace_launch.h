@@ -1,0 +1,27 @@
+// Device-resident trace launch used by the Monte Carlo layer: operator arrays,
+// per-configuration ranges and outputs already live on the device, and the grids
+// are sized for every (configuration, retained state) pair so that no host
+// synchronisation is needed between launches.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+struct hyb_model;
+
+namespace hyb {
+
+// Bytes of workspace trace_resident needs for n_configs configurations.
+size_t trace_ws_bytes(const hyb_model* m, int n_configs);
+
+// Tr_R of configuration c = ops [begin[c], ends[c]) of (tau, flavor, dagger), for
+// c < n_configs, into out_log[c] / out_sign[c].  max_ops bounds every range's
+// length.  Validation and propagation error bits are ORed into *err_accum on the
+// device.  Enqueued on stream s; returns 0 or a negative status (launch errors).
+int trace_resident(hyb_model* m, int n_configs, const int64_t* begin, const int64_t* ends, const double* tau,
+                   const int16_t* flavor, const int8_t* dagger, int max_ops, double beta, void* ws,
+                   double* out_log, int8_t* out_sign, int32_t* err_accum, hipStream_t s);
+
+}  // namespace hyb

@@ -52,6 +52,20 @@ class TraceOutC(C.Structure):
                 ("rows", C.c_void_p), ("on_device", C.c_int32)]
 
 
+class McParamsC(C.Structure):
+    _fields_ = [("n_chains", C.c_int32), ("beta", C.c_double), ("n_delta", C.c_int32),
+                ("delta", C.POINTER(C.c_double)), ("kmax", C.c_int32), ("nmax_ops", C.c_int32),
+                ("seed", C.c_uint64), ("n_tau", C.c_int32), ("meas_every", C.c_int32),
+                ("moves_per_sweep", C.c_int32)]
+
+
+class McStatsC(C.Structure):
+    _fields_ = [("insert_proposed", C.c_int64), ("insert_accepted", C.c_int64),
+                ("remove_proposed", C.c_int64), ("remove_accepted", C.c_int64),
+                ("impossible", C.c_int64), ("zero_weight", C.c_int64), ("moves", C.c_int64),
+                ("order_sum", C.c_double), ("sign_sum", C.c_double)]
+
+
 # name -> (restype, argtypes)
 _P = C.c_void_p
 _SIGS = {
@@ -79,6 +93,16 @@ _SIGS = {
     "hyb_set_timing": (C.c_int, [_P, C.c_int32]),
     "hyb_last_timing": (C.c_int, [_P, _P]),
     "hyb_block_spmm": (C.c_int, [_P, C.c_int32, C.c_int64, _P, _P, _P]),
+    "hyb_mc_create": (C.c_int, [_P, C.POINTER(McParamsC), C.POINTER(_P)]),
+    "hyb_mc_destroy": (C.c_int, [_P]),
+    "hyb_mc_set_configs": (C.c_int, [_P, _P, _P, _P, _P]),
+    "hyb_mc_sweep": (C.c_int, [_P, C.c_int32, _P]),
+    "hyb_mc_get_state": (C.c_int, [_P, _P, _P, _P, _P, _P, _P, _P]),
+    "hyb_mc_get_stats": (C.c_int, [_P, C.POINTER(McStatsC), _P]),
+    "hyb_mc_get_accumulators": (C.c_int, [_P, _P, _P, _P, _P]),
+    "hyb_mc_measure": (C.c_int, [_P, _P, _P, _P]),
+    "hyb_mc_reset_measurements": (C.c_int, [_P, _P]),
+    "hyb_mc_step_count": (C.c_int, [_P, _P]),
     "hyb_last_error": (C.c_char_p, []),
     "hyb_version": (C.c_char_p, []),
 }
@@ -338,3 +362,87 @@ def model_for_workload(w, upload=True, use_cache=True, **kw):
         except HybError:
             pass
     return m
+
+
+class MC:
+    """Monte Carlo chains on the model's device (hyb_mc_*)."""
+
+    def __init__(self, model: Model, n_chains, beta, delta, kmax=48, nmax_ops=1024, seed=7, n_tau=200,
+                 meas_every=1, moves_per_sweep=1):
+        self.model = model
+        self.delta = np.ascontiguousarray(delta, dtype=np.float64)
+        self.n_chains, self.beta, self.kmax, self.n_tau = int(n_chains), float(beta), int(kmax), int(n_tau)
+        self.F = model.info()["n_flavors"]
+        p = McParamsC(self.n_chains, self.beta, len(self.delta) - 1,
+                      self.delta.ctypes.data_as(C.POINTER(C.c_double)), self.kmax, int(nmax_ops),
+                      int(seed), self.n_tau, int(meas_every), int(moves_per_sweep))
+        h = _P()
+        _check(lib().hyb_mc_create(model.h, C.byref(p), C.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().hyb_mc_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_configs(self, chains, stream=None):
+        """chains: list of (cre, ann) with cre[f], ann[f] sequences of times (label order)."""
+        k = np.zeros((self.n_chains, self.F), np.int32)
+        cre = np.zeros((self.n_chains, self.F, self.kmax))
+        ann = np.zeros((self.n_chains, self.F, self.kmax))
+        for c, (cr, an) in enumerate(chains):
+            for f in range(self.F):
+                n = len(cr[f])
+                if n != len(an[f]) or n > self.kmax:
+                    raise ValueError(f"chain {c} flavor {f}: {n} creators, {len(an[f])} annihilators")
+                k[c, f] = n
+                cre[c, f, :n] = cr[f]
+                ann[c, f, :n] = an[f]
+        _check(lib().hyb_mc_set_configs(self.h, _ptr(k), _ptr(cre), _ptr(ann), _stream(stream)))
+
+    def sweep(self, n_sweeps=1, stream=None):
+        _check(lib().hyb_mc_sweep(self.h, int(n_sweeps), _stream(stream)))
+
+    def state(self, with_M=False, stream=None):
+        k = np.zeros((self.n_chains, self.F), np.int32)
+        cre = np.zeros((self.n_chains, self.F, self.kmax))
+        ann = np.zeros((self.n_chains, self.F, self.kmax))
+        M = np.zeros((self.n_chains, self.F, self.kmax, self.kmax)) if with_M else None
+        logw = np.zeros(self.n_chains)
+        sign = np.zeros(self.n_chains, np.int8)
+        _check(lib().hyb_mc_get_state(self.h, _ptr(k), _ptr(cre), _ptr(ann), _ptr(M) if with_M else None,
+                                      _ptr(logw), _ptr(sign), _stream(stream)))
+        return dict(k=k, cre=cre, ann=ann, M=M, logw=logw, sign=sign)
+
+    def stats(self, stream=None):
+        st = McStatsC()
+        _check(lib().hyb_mc_get_stats(self.h, C.byref(st), _stream(stream)))
+        return {name: getattr(st, name) for name, _ in McStatsC._fields_}
+
+    def accumulators(self, stream=None):
+        g = np.zeros((self.n_chains, self.F, self.n_tau))
+        ms = np.zeros(self.n_chains)
+        nm = np.zeros(self.n_chains, np.int64)
+        _check(lib().hyb_mc_get_accumulators(self.h, _ptr(g), _ptr(ms), _ptr(nm), _stream(stream)))
+        return g, ms, nm
+
+    def measure(self, stream=None):
+        G = np.zeros((self.F, self.n_tau))
+        sa = C.c_double()
+        _check(lib().hyb_mc_measure(self.h, _ptr(G), C.byref(sa), _stream(stream)))
+        return G, sa.value
+
+    def reset_measurements(self, stream=None):
+        _check(lib().hyb_mc_reset_measurements(self.h, _stream(stream)))
+
+    def step_count(self):
+        s = C.c_int64()
+        _check(lib().hyb_mc_step_count(self.h, C.byref(s)))
+        return s.value
+

@@ -1,0 +1,184 @@
+"""GPU Monte Carlo (hyb_mc_*) against the oracle's chains, through the C ABI.
+
+The device chains and the oracle's chains draw the same counter-based uniforms,
+so they take the same decisions move by move.  The oracle recomputes every
+weight from scratch, by dense log-determinants and its own trace; the device
+uses O(k^2) determinant updates and the Krylov trace.  Bars:
+- configurations (times, labels, pair numbers): exact;
+- M_f against inv(A_f): 1e-10 relative;
+- log|w|: 1e-10 absolute;
+- signs: exact;
+- G(tau) accumulators: 1e-9 relative.
+The free-orbital run checks G(tau) = G_sc(tau) statistically.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_0908_0681_amd import inputs as I
+from paper_0908_0681_amd import hyb
+from oracle import mc as MC
+from oracle import trace as T
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(autouse=True)
+def announce(request):
+    print(f"\n[gpu-test] {request.node.nodeid}", flush=True)
+    sys.stdout.flush()
+    yield
+
+
+def _require_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _oracle_chains(setup, o, F, kmax):
+    """Initial chains of the setup; a configuration of zero weight starts empty instead."""
+    chains = []
+    for cre, ann in I.mc_initial_configs(setup):
+        try:
+            ch = MC.Chain(o, setup.delta, setup.workload.beta, cre, ann, kmax)
+        except ValueError:
+            ch = MC.Chain(o, setup.delta, setup.workload.beta, [[]] * F, [[]] * F, kmax)
+        chains.append(ch)
+    return chains
+
+
+def _replay_and_compare(which, n_chains, n_moves, kmax=None, n_tau=20, meas_every=3, empty_start=False):
+    _require_gpu()
+    setup = I.mc_setup(which, n_chains)
+    w = setup.workload
+    kmax = kmax or setup.kmax_flavor
+    F = 2 * w.params.n_orb
+    o = T.build(w.params, w.retain_window)
+    m = hyb.model_for_workload(w)
+    mc = hyb.MC(m, setup.n_chains, w.beta, setup.delta, kmax=kmax, nmax_ops=512, seed=setup.seed,
+                n_tau=n_tau, meas_every=meas_every)
+    if empty_start:
+        chains = [MC.Chain(o, setup.delta, w.beta, [[]] * F, [[]] * F, kmax) for _ in range(setup.n_chains)]
+    else:
+        chains = _oracle_chains(setup, o, F, kmax)
+    mc.set_configs([(ch.cre, ch.ann) for ch in chains])
+    st0 = mc.state()
+    for c, ch in enumerate(chains):
+        assert st0["sign"][c] == ch.sign and st0["logw"][c] == pytest.approx(ch.logw, abs=1e-10)
+    mc.sweep(n_moves)
+    acc = np.zeros((setup.n_chains, F, n_tau))
+    margins, accepted = [], 0
+    for step in range(n_moves):
+        for c, ch in enumerate(chains):
+            kind, a = ch.step(MC.move_uniforms(setup.seed, c, step))
+            accepted += a
+            if kind:
+                margins.append(ch.last_margin)
+            if (step + 1) % meas_every == 0:
+                ch.measure(acc[c])
+    assert min(margins) > 1e-8, "a decision within rounding of its threshold: replay not comparable"
+    st = mc.state(with_M=True)
+    worst_M = worst_w = 0.0
+    for c, ch in enumerate(chains):
+        for f in range(F):
+            k = len(ch.cre[f])
+            assert st["k"][c, f] == k, (c, f)
+            assert list(st["cre"][c, f, :k]) == ch.cre[f] and list(st["ann"][c, f, :k]) == ch.ann[f], (c, f)
+            if k:
+                Mi = np.linalg.inv(MC.hyb_matrix(setup.delta, w.beta, ch.cre[f], ch.ann[f]))
+                worst_M = max(worst_M, np.max(np.abs(st["M"][c, f, :k, :k] - Mi)) / np.max(np.abs(Mi)))
+        assert st["sign"][c] == ch.sign, c
+        worst_w = max(worst_w, abs(st["logw"][c] - ch.logw))
+    assert worst_M <= 1e-10 and worst_w <= 1e-10, (worst_M, worst_w)
+    g, ms, nm = mc.accumulators()
+    assert np.all(nm == n_moves // meas_every)
+    assert np.max(np.abs(g - acc)) <= 1e-9 * max(1e-300, np.max(np.abs(acc)))
+    stats = mc.stats()
+    assert stats["moves"] == n_moves * setup.n_chains
+    assert stats["insert_accepted"] + stats["remove_accepted"] == accepted
+    print(f"accepted {accepted} of {n_moves * setup.n_chains}; M {worst_M:.1e}, logw {worst_w:.1e}")
+    mc.close()
+    return accepted
+
+
+def test_mc_two_orbital_trajectory_matches_oracle():
+    assert _replay_and_compare(6, 8, 150) > 50
+
+
+def test_mc_five_orbital_trajectory_matches_oracle():
+    """High initial orders (up to 200 pairs over 10 flavors): large M updates and
+    long operator lists in every trace."""
+    assert _replay_and_compare(3, 4, 12) >= 1
+
+
+def test_mc_capacity_limits_match_oracle():
+    """A pair capacity of 2 per flavor: insertions beyond it are impossible moves on
+    both sides."""
+    _replay_and_compare(6, 4, 120, kmax=2, empty_start=True)
+
+
+def test_mc_free_orbital_green_function():
+    """U = 0, eps = 0: G(tau) = G_sc(tau) = Delta(tau) (t = 1) within the spread
+    over independent chains."""
+    _require_gpu()
+    setup = I.mc_setup(5, 128)
+    w = setup.workload
+    m = hyb.model_for_workload(w)
+    n_tau = 20
+    mc = hyb.MC(m, setup.n_chains, w.beta, setup.delta, kmax=48, nmax_ops=256, seed=setup.seed,
+                n_tau=n_tau, meas_every=2)
+    mc.sweep(500)                 # thermalise
+    mc.reset_measurements()
+    mc.sweep(3000)
+    g, ms, nm = mc.accumulators()
+    h = w.beta / n_tau
+    per_chain = -g / (w.beta * h * ms[:, None, None])
+    mean = per_chain.mean(axis=0)
+    err = per_chain.std(axis=0, ddof=1) / math.sqrt(setup.n_chains)
+    G, sign_avg = mc.measure()
+    assert sign_avg == pytest.approx(1.0)
+    assert np.allclose(G, -g.sum(axis=0) / (w.beta * h * ms.sum()))
+    ref = np.array([np.mean([MC.delta_at(setup.delta, w.beta, x) for x in
+                             np.linspace(b * h, (b + 1) * h, 41)[1:-1]]) for b in range(n_tau)])
+    z = (mean - ref[None, :]) / err
+    print(f"free orbital: max |z| {np.abs(z).max():.2f}, chi2/dof {np.mean(z ** 2):.2f}")
+    assert np.abs(z).max() < 5.0 and np.mean(z ** 2) < 2.5
+    st = mc.stats()
+    assert st["sign_sum"] == st["moves"]          # no sign problem without interactions
+    mc.close()
+
+
+def test_mc_rejects_bad_input():
+    _require_gpu()
+    setup = I.mc_setup(6, 2)
+    w = setup.workload
+    m = hyb.model_for_workload(w)
+    for kw in (dict(kmax=0), dict(kmax=64), dict(nmax_ops=1), dict(n_tau=0)):
+        args = dict(kmax=8, nmax_ops=64, seed=1, n_tau=10, meas_every=1)
+        args.update(kw)
+        with pytest.raises(hyb.HybError) as e:
+            hyb.MC(m, 2, w.beta, setup.delta, **args)
+        assert e.value.code == -1
+    with pytest.raises(hyb.HybError):
+        hyb.MC(m, 2, w.beta, setup.delta[:2], kmax=8)
+    mc = hyb.MC(m, 2, w.beta, setup.delta, kmax=4, nmax_ops=64, seed=1, n_tau=10)
+    F = 4
+    empty = [[] for _ in range(F)]
+    # equal times -> HYB_E_UNSORTED
+    with pytest.raises(hyb.HybError) as e:
+        mc.set_configs([([[1.0], [], [], []], [[1.0], [], [], []]), (empty, empty)])
+    assert e.value.code == -2
+    # three spin-up annihilators in a row leave the sector range of two orbitals:
+    # the trace is a structural zero, so the weight is zero
+    zero = ([[4.0, 5.0], [6.0], [], []], [[1.0, 2.0], [3.0], [], []])
+    with pytest.raises(hyb.HybError) as e:
+        mc.set_configs([zero, (empty, empty)])
+    assert e.value.code == -1
+    # the object stays usable
+    mc.set_configs([(empty, empty), (empty, empty)])
+    mc.sweep(5)
+    assert mc.stats()["moves"] == 10
+    mc.close()
