@@ -144,6 +144,53 @@ def measure_mc(torch, hyb, I, moves=40, warm=10):
     return res
 
 
+def measure_spmm(torch, hyb, I, n_vec=262144, reps=10):
+    """Gated bandwidth benchmark: Y = (H_b - c_b) X on the 7-orbital (n_up, n_dn) =
+    (3, 4) block (1225 states, 8400 off-diagonal entries), FP32, 16-vector panels.
+    With N_v = 262144 X and Y are 1.28 GB each, far beyond the Infinity Cache, so
+    the pass streams HBM.  Algorithmic bytes: 2 d N_v 4 (read X, write Y) plus the
+    block's CSR (values, columns, row pointers, FP64 diagonal).  A plain device
+    copy of the same size is timed alongside; N_v = 8192 (cache-resident, 40 MB) is
+    reported as an effective bandwidth."""
+    w = I.workload(2)
+    m = hyb.model_for_workload(w)
+    n_orb = w.params.n_orb
+    b = 4 * (n_orb + 1) + 3
+    dim, nnz, _ = m.block_info(b)
+    out = {"block": [3, 4], "dim": dim, "nnz_offdiag": nnz}
+    for nv, label in ((n_vec, "hbm"), (8192, "cache_resident")):
+        X = torch.randn(nv // 16, dim, 16, device="cuda", dtype=torch.float32)
+        Y = torch.empty_like(X)
+        for _ in range(2):
+            m.block_spmm(b, X, Y, nv)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            m.block_spmm(b, X, Y, nv)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        byts = 2.0 * dim * nv * 4 + nnz * 8 + dim * 8 + (dim + 1) * 4
+        out[label] = {"n_vec": nv, "ms": ms, "bytes": byts, "GBps": byts / (ms / 1e3) / 1e9,
+                      "frac": byts / (ms / 1e3) / 1e9 / HBM_PEAK_GBS}
+        if label == "hbm":
+            for _ in range(2):
+                Y.copy_(X)
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(reps):
+                Y.copy_(X)
+            e1.record()
+            torch.cuda.synchronize()
+            cms = e0.elapsed_time(e1) / reps
+            out["copy_same_size"] = {"ms": cms, "GBps": 2.0 * X.numel() * 4 / (cms / 1e3) / 1e9}
+            out["target_ms"] = 0.535
+        del X, Y
+        torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(k, n_sample):
     """The FP64 oracle as it stands, on the first n_sample configurations."""
     import numpy as np
@@ -175,6 +222,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=192)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-mc", action="store_true", help="skip the Monte Carlo sweep timing")
+    ap.add_argument("--no-spmm", action="store_true", help="skip the block SpMM bandwidth benchmark")
+    ap.add_argument("--spmm-only", action="store_true", help="only the block SpMM bandwidth benchmark")
     ap.add_argument("--seven", action="store_true", help="also time the 7-orbital mixed workload")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (3 times) and exit: the reference "
@@ -200,6 +249,9 @@ def main():
             y.copy_(x)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": 8 * n, "copy_bytes_written": 8 * n, "launches": 3}), flush=True)
+        return
+    if a.spmm_only:
+        print(json.dumps({"spmm_gated": measure_spmm(torch, hyb, I)}), flush=True)
         return
     r5 = measure_workload(1, a.steps, a.warmup, torch, hyb, I, dump=a.dump)
     # Roofline of the dominant kernel (the path kernel, one launch per batch with the
@@ -242,6 +294,8 @@ def main():
             "feasible_paths")}
     if not a.no_mc:
         line["detail"]["mc"] = measure_mc(torch, hyb, I)
+    if not a.no_spmm:
+        line["detail"]["spmm_gated"] = measure_spmm(torch, hyb, I)
     if not a.no_cpu:
         line["cpu_baseline"] = cpu_baseline(1, a.cpu_sample)
     print(json.dumps(line), flush=True)

@@ -30,6 +30,13 @@ struct DeviceModel {
   double* val64 = nullptr;      // [nnz]
   float* val32 = nullptr;       // [nnz]
   double* diag64 = nullptr;     // [n_states] h_ii - c_b
+  // padded ELL copy of the off-diagonal part, per block [ell_k[b]][dim_b] (column-major
+  // by slot), in-block column as int16 and value as float32; short rows are padded
+  // with their own index and 0
+  int16_t* ell_col = nullptr;
+  float* ell_val32 = nullptr;
+  int16_t* ell_perm = nullptr;  // [dim_b] per block: rows by descending length (ELL row i is row perm[i])
+  int16_t* ell_len = nullptr;   // [dim_b] per block: length of ELL row i
   // retained set
   int32_t* ret_block = nullptr; // [n_ret]
   double* ret_energy = nullptr; // [n_ret]
@@ -66,6 +73,9 @@ struct hyb_model {
   std::vector<double> ret_energy;
   std::vector<int64_t> ret_off;
   std::vector<double> ret_vec;
+  // ELL layout of each block (built at upload): slots per row and offset of the block
+  std::vector<int32_t> ell_k;
+  std::vector<int64_t> ell_off;
   // device side
   bool uploaded = false;
   hyb::DeviceModel dev;

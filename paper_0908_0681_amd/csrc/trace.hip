@@ -228,7 +228,7 @@ void free_device(hyb_model* m) {
   if (!m || !m->uploaded) return;
   DeviceModel& d = m->dev;
   void* ptrs[] = {d.states, d.rank, d.blocks, d.rowptr, d.col, d.val64, d.val32, d.diag64,
-                  d.ret_block, d.ret_energy, d.ret_off, d.ret_vec64, d.ret_vec32, d.ws};
+                  d.ell_col, d.ell_val32, d.ell_perm, d.ell_len, d.ret_block, d.ret_energy, d.ret_off, d.ret_vec64, d.ret_vec32, d.ws};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   for (void*& e : m->events)
@@ -408,6 +408,43 @@ int hyb_model_upload(hyb_model* m, void* stream) {
     }
   std::vector<float> val32(m->val.begin(), m->val.end());
   std::vector<float> rv32(m->ret_vec.begin(), m->ret_vec.end());
+  // ELL copy of each block's off-diagonal rows, rows sorted by descending length
+  // (stable): ELL row i is row perm[i] of the block, slot k of ELL row i at
+  // off + k * dim + i; short rows are padded with their own index and 0
+  m->ell_k.assign(m->n_blocks, 0);
+  m->ell_off.assign(m->n_blocks, 0);
+  int64_t ell_total = 0;
+  for (int b = 0; b < m->n_blocks; ++b) {
+    const BlockDev& B = m->blocks[b];
+    int kmax = 0;
+    for (int r = 0; r < B.dim; ++r)
+      kmax = std::max(kmax, m->rowptr[B.state_off + r + 1] - m->rowptr[B.state_off + r]);
+    m->ell_k[b] = kmax;
+    m->ell_off[b] = ell_total;
+    ell_total += int64_t(kmax) * B.dim;
+  }
+  std::vector<int16_t> ell_col(std::max<int64_t>(ell_total, 1));
+  std::vector<float> ell_val(std::max<int64_t>(ell_total, 1));
+  std::vector<int16_t> ell_perm(std::max<int64_t>(m->n_states, 1)), ell_len(std::max<int64_t>(m->n_states, 1));
+  for (int b = 0; b < m->n_blocks; ++b) {
+    const BlockDev& B = m->blocks[b];
+    std::vector<int> order(B.dim);
+    for (int r = 0; r < B.dim; ++r) order[r] = r;
+    auto len = [&](int r) { return m->rowptr[B.state_off + r + 1] - m->rowptr[B.state_off + r]; };
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return len(x) > len(y); });
+    for (int i = 0; i < B.dim; ++i) {
+      const int r = order[i];
+      const int g = B.state_off + r;
+      const int n = len(r);
+      ell_perm[B.state_off + i] = int16_t(r);
+      ell_len[B.state_off + i] = int16_t(n);
+      for (int k = 0; k < m->ell_k[b]; ++k) {
+        const int64_t at = m->ell_off[b] + int64_t(k) * B.dim + i;
+        ell_col[at] = int16_t(k < n ? m->col[m->rowptr[g] + k] : r);
+        ell_val[at] = k < n ? float(m->val[m->rowptr[g] + k]) : 0.0f;
+      }
+    }
+  }
   m->uploaded = true;  // so that free_device releases partial uploads
   if ((rc = dev_upload(d.states, m->states.data(), m->states.size(), s))) return rc;
   if ((rc = dev_upload(d.rank, m->rank.data(), m->rank.size(), s))) return rc;
@@ -417,6 +454,10 @@ int hyb_model_upload(hyb_model* m, void* stream) {
   if ((rc = dev_upload(d.val64, m->val.data(), m->val.size(), s))) return rc;
   if ((rc = dev_upload(d.val32, val32.data(), val32.size(), s))) return rc;
   if ((rc = dev_upload(d.diag64, diag_shifted.data(), diag_shifted.size(), s))) return rc;
+  if ((rc = dev_upload(d.ell_col, ell_col.data(), ell_col.size(), s))) return rc;
+  if ((rc = dev_upload(d.ell_val32, ell_val.data(), ell_val.size(), s))) return rc;
+  if ((rc = dev_upload(d.ell_perm, ell_perm.data(), ell_perm.size(), s))) return rc;
+  if ((rc = dev_upload(d.ell_len, ell_len.data(), ell_len.size(), s))) return rc;
   if ((rc = dev_upload(d.ret_block, m->ret_block.data(), m->ret_block.size(), s))) return rc;
   if ((rc = dev_upload(d.ret_energy, m->ret_energy.data(), m->ret_energy.size(), s))) return rc;
   if ((rc = dev_upload(d.ret_off, m->ret_off.data(), m->ret_off.size(), s))) return rc;
