@@ -80,11 +80,12 @@ def u01(a: int, b: int) -> float:
     return ((a >> 5) * 67108864 + (b >> 6)) / 9007199254740992.0
 
 
-def move_uniforms(seed: int, chain: int, step: int):
-    """u0..u5 of one move: three Philox calls (call index 0, 1, 2)."""
+def move_uniforms(seed: int, chain: int, step: int, calls=(0, 1, 2)):
+    """u0..u5 of one move: three Philox calls (call index 0, 1, 2); the learned
+    proposal also draws calls 3 and 4 (u6..u9)."""
     key = (seed & M32, (seed >> 32) & M32)
     out = []
-    for call in range(3):
+    for call in calls:
         w = philox4x32_10((step & M32, (step >> 32) & M32, chain, call), key)
         out += [u01(w[0], w[1]), u01(w[2], w[3])]
     return out
@@ -172,8 +173,9 @@ def weight(tr: TraceOracle, table, beta, cre, ann):
 class Chain:
     """State: cre[f], ann[f] (label order), the weight's sign and log|w|."""
 
-    def __init__(self, tr: TraceOracle, table, beta, cre, ann, kmax: int):
+    def __init__(self, tr: TraceOracle, table, beta, cre, ann, kmax: int, net=None, eps: float = 0.1):
         self.tr, self.table, self.beta, self.kmax = tr, table, float(beta), kmax
+        self.net, self.eps = net, eps     # learned insertion density (oracle.mlp.Network) or None
         self.cre = [list(map(float, c)) for c in cre]
         self.ann = [list(map(float, a)) for a in ann]
         self.sign, self.logw = weight(tr, table, beta, self.cre, self.ann)
@@ -195,22 +197,41 @@ class Chain:
                 return 0, None, None, 0, -np.inf, -np.inf
             ts = u[2] * self.beta
             te = ts + u[3] * self.beta
+            if self.net is None:
+                log_factor = 2.0 * (np.log(self.beta) - np.log(k + 1))
+            else:
+                from . import mlp as NN
+                ux = u[6:10]
+                z = self.net.forward(NN.features(self.cre, self.ann, f, self.beta)[None])["Z3"][0]
+                length = u[3] * self.beta
+                if not ux[2] < self.eps:
+                    bs, bl = _draw_bin(z[:NN.BINS], u[2]), _draw_bin(z[NN.BINS:], u[3])
+                    ts = (bs + ux[0]) * (self.beta / NN.BINS)
+                    length = (bl + ux[1]) * (self.beta / NN.BINS)
+                te = ts + length
+                log_factor = -2.0 * np.log(k + 1) - NN.logq(z, ts, length, self.beta, self.eps)
             if te >= self.beta:
                 te -= self.beta
             cre[f].append(ts)
             ann[f].append(te)
-            log_factor = 2.0 * (np.log(self.beta) - np.log(k + 1))
             kind = 1
         else:
             if k == 0:
                 return 0, None, None, 0, -np.inf, -np.inf
             i = min(int(u[2] * k), k - 1)
             j = min(int(u[3] * k), k - 1)
+            if self.net is not None:
+                from . import mlp as NN
+                z = self.net.forward(NN.features(self.cre, self.ann, f, self.beta, exclude=(f, i, j))[None])["Z3"][0]
+                length = self.ann[f][j] - self.cre[f][i]
+                if length < 0.0:
+                    length += self.beta
+                lq = NN.logq(z, self.cre[f][i], length, self.beta, self.eps)
             cre[f][i] = cre[f][k - 1]
             cre[f].pop()
             ann[f][j] = ann[f][k - 1]
             ann[f].pop()
-            log_factor = 2.0 * (np.log(k) - np.log(self.beta))
+            log_factor = 2.0 * (np.log(k) - np.log(self.beta)) if self.net is None else 2.0 * np.log(k) + lq
             kind = 2
         s, lw = weight(self.tr, self.table, self.beta, cre, ann)
         if s == 0:
@@ -248,6 +269,14 @@ class Chain:
                         s = -1.0
                     b = min(int(d / self.beta * n_tau), n_tau - 1)
                     acc[f, b] += self.sign * s * M[j, i]
+
+
+def _draw_bin(z, u: float) -> int:
+    """Inverse-CDF draw of a bin from logits z with uniform u."""
+    e = np.exp(np.asarray(z, dtype=np.float64) - np.max(z))
+    c = np.cumsum(e)
+    b = int(np.searchsorted(c, u * c[-1], side="right"))
+    return min(b, len(z) - 1)
 
 
 def g_tau(acc_sum: np.ndarray, sign_sum: float, beta: float) -> np.ndarray:
