@@ -300,6 +300,45 @@ int hyb_mc_measure(const hyb_mc* mc, double* G, double* sign_avg, void* stream);
 int hyb_mc_reset_measurements(hyb_mc* mc, void* stream);
 int hyb_mc_step_count(const hyb_mc* mc, int64_t* step);
 
+/* ---- learned insertion proposal ---------------------------------------------- */
+
+/* A 3-layer perceptron 352 -> 128 -> 128 -> 128 (ReLU between layers) mapping the
+ * features of (configuration without the pair, flavor f) to 64 logits for the bin
+ * of the creator time tau_s and 64 logits for the bin of the pair length
+ * l = (tau_e - tau_s) mod beta.  Features: one-hot f (F entries), k_g / 32 for every
+ * flavor (F), and per flavor the count of creators minus annihilators before the
+ * centre of each of 32 equal time bins (32 F); zero-padded to 352 (F <= 10).
+ * BF16 weights and activations on the matrix cores with FP32 accumulation; FP32
+ * master weights.  Insertion density
+ *   q(tau_s, l) = (1 - eps) p_tau(bin tau_s) (64/beta) p_l(bin l) (64/beta) + eps / beta^2.
+ * Training target: cross-entropy of the two bins of a pair removed uniformly from a
+ * sampled configuration (maximum likelihood of the pairs the chains produce).
+ * Weight layout (FP32, output-major): W1 [128][352], W2 [128][128], W3 [128][128]
+ * concatenated; biases b1 [128], b2 [128], b3 [128] concatenated. */
+typedef struct hyb_mlp hyb_mlp;
+int hyb_mlp_create(uint64_t seed, hyb_mlp** out);   /* He-uniform weights from seed, zero biases */
+int hyb_mlp_destroy(hyb_mlp* p);
+int hyb_mlp_get_weights(const hyb_mlp* p, float* w, float* b);   /* host outputs */
+int hyb_mlp_set_weights(hyb_mlp* p, const float* w, const float* b);   /* host inputs; resets Adam */
+/* logits [n][128] (device) of features X [n][352] (device, bf16) */
+int hyb_mlp_forward(hyb_mlp* p, int32_t n, const void* X, float* logits, void* stream);
+/* Gradients of the mean loss over the batch (host outputs, may be NULL; same layouts
+ * as the weights) and the mean loss; X device bf16 [n][352], targets device [n][2]. */
+int hyb_mlp_gradients(hyb_mlp* p, int32_t n, const void* X, const int32_t* targets, float* w_grad, float* b_grad,
+                      float* loss, void* stream);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on a batch; *loss (host, may be
+ * NULL) = mean loss before the step. */
+int hyb_mlp_train_step(hyb_mlp* p, int32_t n, const void* X, const int32_t* targets, float lr, float* loss,
+                       void* stream);
+/* Use the network (NULL: back to uniform insertion) with mixture weight eps in (0, 1]
+ * for every following insertion / removal of mc.  The network must outlive its use. */
+int hyb_mc_attach_mlp(hyb_mc* mc, hyb_mlp* mlp, double eps);
+/* One training sample per chain from the current states: X [n_chains][352] (device,
+ * bf16) and targets [n_chains][2] (device; (-1, -1) for a chain without pairs).  The
+ * flavor (uniform among those with pairs) and the pair come from Philox calls 8 and 9
+ * at counter `index`. */
+int hyb_mc_harvest(hyb_mc* mc, int64_t index, void* X, int32_t* targets, void* stream);
+
 /* ---- misc ------------------------------------------------------------------ */
 const char* hyb_last_error(void);
 const char* hyb_version(void);

@@ -47,6 +47,12 @@ __global__ __launch_bounds__(64) void k_mc_accept(MCParams Q, int64_t step, int 
   mc_accept(Q, blockIdx.x, step, measure, canon);
 }
 
+__global__ __launch_bounds__(64) void k_mc_choose(MCParams Q, int64_t step) { mc_choose(Q, blockIdx.x, step); }
+
+__global__ __launch_bounds__(64) void k_mc_harvest(MCParams Q, int64_t index, __bf16* X, int32_t* T) {
+  mc_harvest(Q, blockIdx.x, index, X, T);
+}
+
 }  // namespace hyb
 
 // ---------------------------------------------------------------------------
@@ -63,6 +69,9 @@ struct hyb_mc {
   int8_t* t_sign = nullptr;
   int32_t* err = nullptr;
   void* trace_ws = nullptr;
+  hyb_mlp* mlp = nullptr;      // learned proposal (NULL: uniform)
+  __bf16* X = nullptr;         // [C][MLP_IN] features of the proposing configurations
+  float* logits = nullptr;     // [C][MLP_OUT]
   std::vector<void*> allocs;
 };
 
@@ -352,6 +361,13 @@ int hyb_mc_sweep(hyb_mc* mc, int32_t n_sweeps, void* stream) {
   const int64_t moves = int64_t(n_sweeps) * mc->p.moves_per_sweep;
   for (int64_t mv = 0; mv < moves; ++mv) {
     const int64_t step = mc->step;
+    if (mc->mlp) {
+      k_mc_choose<<<C, 64, 0, s>>>(mc->Q, step);
+      MlpActs a = mc->mlp->acts;
+      a.z3 = mc->logits;
+      int rc0 = mlp_forward(mc->mlp, C, mc->X, a, s);
+      if (rc0) return rc0;
+    }
     k_mc_propose<<<C, 64, 0, s>>>(mc->Q, step);
     int rc = run_traces(mc, s);
     if (rc) return rc;
@@ -464,6 +480,37 @@ int hyb_mc_reset_measurements(hyb_mc* mc, void* stream) {
   MC_HIP_TRY(hipMemsetAsync(mc->Q.stats, 0, sizeof(int64_t) * size_t(C) * ST_N, s));
   MC_HIP_TRY(hipMemsetAsync(mc->Q.sign_sum, 0, sizeof(double) * C, s));
   MC_HIP_TRY(hipStreamSynchronize(s));
+  return HYB_OK;
+}
+
+int hyb_mc_attach_mlp(hyb_mc* mc, hyb_mlp* mlp, double eps) {
+  if (!mc) return set_error(HYB_E_ARG, "NULL argument");
+  if (mlp && !(eps > 0.0 && eps <= 1.0)) return set_error(HYB_E_ARG, "mixture weight eps must be in (0, 1]");
+  if (mlp && mc->F > 10) return set_error(HYB_E_ARG, "the learned proposal takes at most 10 flavors");
+  const int C = mc->p.n_chains;
+  if (mlp && !mc->X) {
+    int rc = 0;
+    if ((rc = mc_alloc(mc, mc->X, size_t(C) * MLP_IN)) || (rc = mc_alloc(mc, mc->logits, size_t(C) * MLP_OUT)))
+      return rc;
+  }
+  if (mlp) {
+    int rc = mlp_ensure(mlp, C);
+    if (rc) return rc;
+  }
+  mc->mlp = mlp;
+  mc->Q.learned = mlp ? 1 : 0;
+  mc->Q.eps_mix = eps;
+  mc->Q.X = mc->X;
+  mc->Q.logits = mc->logits;
+  return HYB_OK;
+}
+
+int hyb_mc_harvest(hyb_mc* mc, int64_t index, void* X, int32_t* targets, void* stream) {
+  if (!mc || !X || !targets) return set_error(HYB_E_ARG, "NULL argument");
+  if (mc->F > 10) return set_error(HYB_E_ARG, "the learned proposal takes at most 10 flavors");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  k_mc_harvest<<<mc->p.n_chains, 64, 0, s>>>(mc->Q, index, static_cast<__bf16*>(X), targets);
+  MC_HIP_TRY(hipGetLastError());
   return HYB_OK;
 }
 

@@ -5,6 +5,7 @@
 #pragma once
 
 #include "trace_kernels.h"
+#include "mlp_kernels.h"
 
 // Operator times, table positions and acceptance ratios are computed with one
 // rounding per operation (no fused multiply-add), so that they are the same
@@ -24,6 +25,7 @@ struct MoveRec {
   int32_t pad;
   double ts, te;  // insert: creator / annihilator times
   double ratio;   // det A_f' / det A_f (with the relabelling of a removal)
+  double logq;    // learned proposal: log q(tau_s, l) of the inserted / removed pair
 };
 
 enum : int { ST_INS_PROP = 0, ST_INS_ACC, ST_REM_PROP, ST_REM_ACC, ST_IMPOSSIBLE, ST_ZERO, ST_ORDER, ST_MOVES, ST_N };
@@ -61,6 +63,11 @@ struct MCParams {
   double* gacc;       // [C][F][n_tau]
   double* meas_sign;  // [C]
   int64_t* n_meas;    // [C]
+  // learned proposal (learned != 0): features [C][MLP_IN] and logits [C][MLP_OUT]
+  int32_t learned;
+  double eps_mix;
+  __bf16* X;
+  const float* logits;
 };
 
 // ---- generator -------------------------------------------------------------
@@ -96,6 +103,74 @@ __device__ inline void move_uniforms(const MCParams& Q, int chain, int64_t step,
     u[2 * call] = u01(c[0], c[1]);
     u[2 * call + 1] = u01(c[2], c[3]);
   }
+}
+
+// u6..u9 of a move (calls 3 and 4), drawn only by the learned proposal.
+__device__ inline void move_uniforms_extra(const MCParams& Q, int chain, int64_t step, double (&u)[4]) {
+#pragma unroll
+  for (int call = 3; call < 5; ++call) {
+    uint32_t c[4] = {uint32_t(uint64_t(step)), uint32_t(uint64_t(step) >> 32), uint32_t(chain), uint32_t(call)};
+    philox4x32_10(c, Q.key0, Q.key1);
+    u[2 * (call - 3)] = u01(c[0], c[1]);
+    u[2 * (call - 3) + 1] = u01(c[2], c[3]);
+  }
+}
+
+// ---- learned proposal ---------------------------------------------------------
+
+// Softmax probability of bin b among the 64 logits z[0..64) (uniform over lanes).
+__device__ inline void softmax64(const float* z, float& mx, float& sum) {
+  mx = z[0];
+  for (int q = 1; q < MLP_BINS; ++q) mx = fmaxf(mx, z[q]);
+  sum = 0.0f;
+  for (int q = 0; q < MLP_BINS; ++q) sum += expf(z[q] - mx);
+}
+
+// log q(ts, l) = log[(1 - eps) p_tau(bin ts) (64/beta) p_l(bin l) (64/beta) + eps / beta^2]
+__device__ inline double mlp_logq(const MCParams& Q, const float* z, double ts, double l) {
+  float m0, s0, m1, s1;
+  softmax64(z, m0, s0);
+  softmax64(z + MLP_BINS, m1, s1);
+  int bs = int(ts / Q.beta * MLP_BINS), bl = int(l / Q.beta * MLP_BINS);
+  bs = bs > MLP_BINS - 1 ? MLP_BINS - 1 : bs;
+  bl = bl > MLP_BINS - 1 ? MLP_BINS - 1 : bl;
+  const double pt = double(expf(z[bs] - m0) / s0), pl = double(expf(z[MLP_BINS + bl] - m1) / s1);
+  const double d = MLP_BINS / Q.beta;
+  return log((1.0 - Q.eps_mix) * pt * d * pl * d + Q.eps_mix / (Q.beta * Q.beta));
+}
+
+// Inverse-CDF draw of a bin from 64 logits with uniform u.
+__device__ inline int mlp_draw_bin(const float* z, double u) {
+  float mx, sum;
+  softmax64(z, mx, sum);
+  const double target = u * double(sum);
+  double acc = 0.0;
+  for (int q = 0; q < MLP_BINS - 1; ++q) {
+    acc += double(expf(z[q] - mx));
+    if (target < acc) return q;
+  }
+  return MLP_BINS - 1;
+}
+
+// Phase A of a learned move: the move type, flavor and (for a removal) the pair,
+// and the features of the configuration the pair is inserted into / removed from.
+__device__ inline void mc_choose(const MCParams& Q, int c, int64_t step) {
+  double u[6];
+  move_uniforms(Q, c, step, u);
+  const int F = Q.F, KM = Q.kmax;
+  int f = int(__dmul_rn(u[0], double(F)));
+  if (f > F - 1) f = F - 1;
+  const bool ins = u[1] < 0.5;
+  const int k = Q.kf[c * F + f];
+  int i = -1, j = -1;
+  if (!ins && k > 0) {
+    i = int(__dmul_rn(u[2], double(k)));
+    j = int(__dmul_rn(u[3], double(k)));
+    if (i > k - 1) i = k - 1;
+    if (j > k - 1) j = k - 1;
+  }
+  mlp_features(F, KM, Q.beta, Q.kf + c * F, Q.cre + int64_t(c) * F * KM, Q.ann + int64_t(c) * F * KM, f,
+               (i >= 0) ? f : -1, i, j, Q.X + int64_t(c) * MLP_IN);
 }
 
 // ---- bath --------------------------------------------------------------------
@@ -150,8 +225,25 @@ __device__ inline void mc_propose(const MCParams& Q, int c, int64_t step, double
     if (k >= KM || n + 2 > NM) {
       rec.kind = 0;
     } else {
-      const double ts = __dmul_rn(u[2], Q.beta);
+      double ts = __dmul_rn(u[2], Q.beta);
       double te = __dadd_rn(ts, __dmul_rn(u[3], Q.beta));
+      if (Q.learned) {
+        // mixture: eps uniform on [0, beta)^2, else bins from the network and a
+        // uniform position inside each bin
+        const float* z = Q.logits + int64_t(c) * MLP_OUT;
+        double ux[4];
+        move_uniforms_extra(Q, c, step, ux);
+        double len = __dmul_rn(u[3], Q.beta);
+        if (!(ux[2] < Q.eps_mix)) {
+          const int bs = mlp_draw_bin(z, u[2]), bl = mlp_draw_bin(z + MLP_BINS, u[3]);
+          ts = (bs + ux[0]) * (Q.beta / MLP_BINS);
+          len = (bl + ux[1]) * (Q.beta / MLP_BINS);
+          if (ts >= Q.beta) ts = nextafter(Q.beta, 0.0);   // a position that rounded up to beta
+          if (len >= Q.beta) len = nextafter(Q.beta, 0.0);
+        }
+        te = ts + len;
+        rec.logq = mlp_logq(Q, z, ts, len);
+      }
       if (te >= Q.beta) te = __dadd_rn(te, -Q.beta);
       rec.ts = ts;
       rec.te = te;
@@ -222,6 +314,11 @@ __device__ inline void mc_propose(const MCParams& Q, int c, int64_t step, double
       const double s_i = (i != k - 1) ? -1.0 : 1.0, s_j = (j != k - 1) ? -1.0 : 1.0;
       rec.ratio = s_i * s_j * Mf[j * KM + i];
       const double tc = cre_f[i], ta = ann_f[j];
+      if (Q.learned) {
+        double len = ta - tc;
+        if (len < 0.0) len += Q.beta;
+        rec.logq = mlp_logq(Q, Q.logits + int64_t(c) * MLP_OUT, tc, len);
+      }
       double pc = 0.0, pa = 0.0;
       for (int p = lane; p < n; p += 64) {
         if (otau[p] == tc && ofl[p] == f && odg[p] == 1) pc = double(p);
@@ -285,8 +382,13 @@ __device__ inline void mc_accept(const MCParams& Q, int c, int64_t step, int mea
   int64_t* st = Q.stats + int64_t(c) * ST_N;
   bool accept = false;
   if (rec.kind != 0 && rec.valid && Q.t_sign[c] != 0 && rec.ratio != 0.0) {
-    const double log_factor = (rec.kind == 1) ? 2.0 * (log(Q.beta) - log(double(k + 1)))
-                                              : 2.0 * (log(double(k)) - log(Q.beta));
+    // Metropolis-Hastings factor q_reverse / q_forward: removal picks one of k^2
+    // pairs; insertion has density 1 / beta^2 (uniform) or q(tau_s, l) (learned)
+    double log_factor;
+    if (Q.learned)
+      log_factor = (rec.kind == 1) ? -2.0 * log(double(k + 1)) - rec.logq : 2.0 * log(double(k)) + rec.logq;
+    else
+      log_factor = (rec.kind == 1) ? 2.0 * (log(Q.beta) - log(double(k + 1))) : 2.0 * (log(double(k)) - log(Q.beta));
     const double log_ratio = (Q.t_log[c] - Q.cur_logtr[c]) + log(fabs(rec.ratio)) + log_factor;
     accept = u[4] < exp(log_ratio);
   }
@@ -394,6 +496,56 @@ __device__ inline void mc_accept(const MCParams& Q, int c, int64_t step, int mea
       Q.meas_sign[c] += sgn;
       Q.n_meas[c] += 1;
     }
+  }
+}
+
+// One training sample per chain: a flavor with pairs (uniform among them), one of
+// its k^2 (creator, annihilator) pairs (uniform), the features of the configuration
+// without that pair, and the targets (bin of tau_s, bin of l) on 64 bins.  Chains
+// without pairs give targets (-1, -1).  Uniforms: Philox calls 8 and 9 at counter
+// `index`.
+__device__ inline void mc_harvest(const MCParams& Q, int c, int64_t index, __bf16* X, int32_t* T) {
+  double u[4];
+#pragma unroll
+  for (int call = 8; call < 10; ++call) {
+    uint32_t w[4] = {uint32_t(uint64_t(index)), uint32_t(uint64_t(index) >> 32), uint32_t(c), uint32_t(call)};
+    philox4x32_10(w, Q.key0, Q.key1);
+    u[2 * (call - 8)] = u01(w[0], w[1]);
+    u[2 * (call - 8) + 1] = u01(w[2], w[3]);
+  }
+  const int F = Q.F, KM = Q.kmax;
+  const int32_t* kf = Q.kf + c * F;
+  int nonempty = 0;
+  for (int g = 0; g < F; ++g) nonempty += kf[g] > 0;
+  if (nonempty == 0) {
+    if (threadIdx.x == 0) {
+      T[2 * c] = -1;
+      T[2 * c + 1] = -1;
+    }
+    return;
+  }
+  int pick = int(u[0] * nonempty);
+  if (pick > nonempty - 1) pick = nonempty - 1;
+  int f = 0;
+  for (int g = 0, seen = 0; g < F; ++g)
+    if (kf[g] > 0) {
+      if (seen == pick) f = g;
+      ++seen;
+    }
+  const int k = kf[f];
+  int i = int(u[1] * k), j = int(u[2] * k);
+  if (i > k - 1) i = k - 1;
+  if (j > k - 1) j = k - 1;
+  const double* cre = Q.cre + int64_t(c) * F * KM;
+  const double* ann = Q.ann + int64_t(c) * F * KM;
+  mlp_features(F, KM, Q.beta, kf, cre, ann, f, f, i, j, X + int64_t(c) * MLP_IN);
+  if (threadIdx.x == 0) {
+    const double ts = cre[f * KM + i];
+    double len = ann[f * KM + j] - ts;
+    if (len < 0.0) len += Q.beta;
+    int bs = int(ts / Q.beta * MLP_BINS), bl = int(len / Q.beta * MLP_BINS);
+    T[2 * c] = bs > MLP_BINS - 1 ? MLP_BINS - 1 : bs;
+    T[2 * c + 1] = bl > MLP_BINS - 1 ? MLP_BINS - 1 : bl;
   }
 }
 

@@ -103,6 +103,15 @@ _SIGS = {
     "hyb_mc_measure": (C.c_int, [_P, _P, _P, _P]),
     "hyb_mc_reset_measurements": (C.c_int, [_P, _P]),
     "hyb_mc_step_count": (C.c_int, [_P, _P]),
+    "hyb_mc_attach_mlp": (C.c_int, [_P, _P, C.c_double]),
+    "hyb_mc_harvest": (C.c_int, [_P, C.c_int64, _P, _P, _P]),
+    "hyb_mlp_create": (C.c_int, [C.c_uint64, C.POINTER(_P)]),
+    "hyb_mlp_destroy": (C.c_int, [_P]),
+    "hyb_mlp_get_weights": (C.c_int, [_P, _P, _P]),
+    "hyb_mlp_set_weights": (C.c_int, [_P, _P, _P]),
+    "hyb_mlp_forward": (C.c_int, [_P, C.c_int32, _P, _P, _P]),
+    "hyb_mlp_gradients": (C.c_int, [_P, C.c_int32, _P, _P, _P, _P, _P, _P]),
+    "hyb_mlp_train_step": (C.c_int, [_P, C.c_int32, _P, _P, C.c_float, _P, _P]),
     "hyb_last_error": (C.c_char_p, []),
     "hyb_version": (C.c_char_p, []),
 }
@@ -445,4 +454,76 @@ class MC:
         s = C.c_int64()
         _check(lib().hyb_mc_step_count(self.h, C.byref(s)))
         return s.value
+
+    def attach_mlp(self, mlp, eps=0.1):
+        """Learned insertion proposal (mlp: MLP or None for uniform)."""
+        self._mlp = mlp
+        _check(lib().hyb_mc_attach_mlp(self.h, mlp.h if mlp is not None else None, float(eps)))
+
+    def harvest(self, index, X, T, stream=None):
+        """One training sample per chain into device tensors X [n_chains][352] (bf16)
+        and T [n_chains][2] (int32)."""
+        _check(lib().hyb_mc_harvest(self.h, int(index), _ptr(X), _ptr(T), _stream(stream)))
+
+
+MLP_IN, MLP_H, MLP_OUT, MLP_BINS = 352, 128, 128, 64
+MLP_W_SHAPES = [(MLP_H, MLP_IN), (MLP_H, MLP_H), (MLP_OUT, MLP_H)]
+MLP_B_SHAPES = [(MLP_H,), (MLP_H,), (MLP_OUT,)]
+
+
+class MLP:
+    """The learned proposal network (hyb_mlp_*); weights as lists of numpy arrays."""
+
+    def __init__(self, seed=1):
+        h = _P()
+        _check(lib().hyb_mlp_create(int(seed), C.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().hyb_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def _split(flat, shapes):
+        out, o = [], 0
+        for sh in shapes:
+            n = int(np.prod(sh))
+            out.append(flat[o:o + n].reshape(sh).copy())
+            o += n
+        return out
+
+    def weights(self):
+        w = np.zeros(sum(int(np.prod(s)) for s in MLP_W_SHAPES), np.float32)
+        b = np.zeros(sum(int(np.prod(s)) for s in MLP_B_SHAPES), np.float32)
+        _check(lib().hyb_mlp_get_weights(self.h, _ptr(w), _ptr(b)))
+        return self._split(w, MLP_W_SHAPES), self._split(b, MLP_B_SHAPES)
+
+    def set_weights(self, Ws, bs):
+        w = np.ascontiguousarray(np.concatenate([np.asarray(x, np.float32).ravel() for x in Ws]))
+        b = np.ascontiguousarray(np.concatenate([np.asarray(x, np.float32).ravel() for x in bs]))
+        _check(lib().hyb_mlp_set_weights(self.h, _ptr(w), _ptr(b)))
+
+    def forward(self, X, logits, stream=None):
+        _check(lib().hyb_mlp_forward(self.h, int(X.shape[0]), _ptr(X), _ptr(logits), _stream(stream)))
+
+    def gradients(self, X, T, stream=None):
+        w = np.zeros(sum(int(np.prod(s)) for s in MLP_W_SHAPES), np.float32)
+        b = np.zeros(sum(int(np.prod(s)) for s in MLP_B_SHAPES), np.float32)
+        loss = C.c_float()
+        _check(lib().hyb_mlp_gradients(self.h, int(X.shape[0]), _ptr(X), _ptr(T), _ptr(w), _ptr(b),
+                                       C.byref(loss), _stream(stream)))
+        return self._split(w, MLP_W_SHAPES), self._split(b, MLP_B_SHAPES), loss.value
+
+    def train_step(self, X, T, lr, want_loss=False, stream=None):
+        loss = C.c_float()
+        _check(lib().hyb_mlp_train_step(self.h, int(X.shape[0]), _ptr(X), _ptr(T), float(lr),
+                                        C.byref(loss) if want_loss else None, _stream(stream)))
+        return loss.value if want_loss else None
 
