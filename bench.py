@@ -191,6 +191,87 @@ def measure_spmm(torch, hyb, I, n_vec=262144, reps=10):
     return out
 
 
+def _g_half(mc, beta, n_tau):
+    """Per chain: the sign-weighted flavor average of G(tau) over the two bins at beta/2."""
+    g, ms, nm = mc.accumulators()
+    G = -g / (beta * (beta / n_tau) * ms[:, None, None])
+    return G[:, :, n_tau // 2 - 1:n_tau // 2 + 1].mean(axis=(1, 2)), nm
+
+
+def measure_ess(torch, hyb, I, therm=2000, harvests=100, train_steps=1000, moves=1000, n_tau=20):
+    """Effective samples per second of G(beta/2), learned vs uniform insertion, on the
+    5-orbital model with the semicircular bath (256 chains).  Both samplers start from
+    the same thermalised uniform-sampler state.  ESS = n_chains * var(one measurement)
+    / var(chain mean) (chains are independent; the single-measurement variance is
+    taken across chains at one measurement); wall time includes the network's
+    inference.  The network is trained beforehand on pairs harvested from the uniform
+    chains (time reported separately)."""
+    import numpy as np
+    setup = I.mc_setup(3)
+    w = setup.workload
+    m = hyb.model_for_workload(w)
+    mk = lambda seed: hyb.MC(m, setup.n_chains, w.beta, setup.delta, kmax=setup.kmax_flavor, nmax_ops=512,
+                             seed=seed, n_tau=n_tau, meas_every=1)
+    F = 2 * w.params.n_orb
+    chains = I.mc_initial_configs(setup)
+    r = m.trace_batch(I.from_lists([I.mc_merged(cre, ann) for cre, ann in chains], w.beta))
+    chains = [ch if r.sign[c] != 0 else ([[]] * F, [[]] * F) for c, ch in enumerate(chains)]
+    base = mk(setup.seed)
+    base.set_configs(chains)
+    base.sweep(therm)
+    # training pairs from the uniform chains
+    t0 = time.perf_counter()
+    Xs, Ts = [], []
+    for hv in range(harvests):
+        X = torch.zeros(setup.n_chains, hyb.MLP_IN, device="cuda", dtype=torch.bfloat16)
+        T = torch.zeros(setup.n_chains, 2, device="cuda", dtype=torch.int32)
+        base.harvest(hv, X, T)
+        base.sweep(2)
+        Xs.append(X)
+        Ts.append(T)
+    X, T = torch.cat(Xs), torch.cat(Ts)
+    keep = T[:, 0] >= 0
+    X, T = X[keep].contiguous(), T[keep].contiguous()
+    net = hyb.MLP(seed=2024)
+    gen = torch.Generator(device="cuda").manual_seed(7)
+    for it in range(train_steps):
+        idx = torch.randint(0, X.shape[0], (512,), device="cuda", generator=gen)
+        net.train_step(X[idx].contiguous(), T[idx].contiguous(), 2e-3)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    st = base.state()
+    start = [([list(st["cre"][c, f, :st["k"][c, f]]) for f in range(F)],
+              [list(st["ann"][c, f, :st["k"][c, f]]) for f in range(F)]) for c in range(setup.n_chains)]
+    base.close()
+    out = {"workload": setup.name, "n_chains": setup.n_chains, "observable": "G(beta/2), flavor average",
+           "training": {"samples": int(X.shape[0]), "steps": train_steps, "batch": 512, "seconds": train_s}}
+    for mode, seed in (("uniform", setup.seed + 1), ("learned", setup.seed + 1)):
+        mc = mk(seed)
+        mc.set_configs(start)
+        if mode == "learned":
+            mc.attach_mlp(net, eps=0.1)
+        mc.sweep(1)
+        one, _ = _g_half(mc, w.beta, n_tau)           # one measurement per chain
+        mc.reset_measurements()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        mc.sweep(moves)
+        dt = time.perf_counter() - t1
+        means, nm = _g_half(mc, w.beta, n_tau)
+        ok = np.isfinite(one) & np.isfinite(means)
+        var1, varm = float(np.var(one[ok], ddof=1)), float(np.var(means[ok], ddof=1))
+        ess = float(ok.sum() * min(var1 / varm, float(moves))) if varm > 0 else float("nan")
+        s2 = mc.stats()
+        out[mode] = {"moves": moves, "wall_s": dt, "ess": ess, "ess_per_s": ess / dt,
+                     "acceptance": (s2["insert_accepted"] + s2["remove_accepted"]) / max(1, s2["moves"]),
+                     "mean_order": s2["order_sum"] / max(1, s2["moves"]), "sign_avg": s2["sign_sum"] / max(1, s2["moves"]),
+                     "g_half": float(np.mean(means[ok]))}
+        mc.close()
+    out["learned_over_uniform_ess_per_s"] = out["learned"]["ess_per_s"] / out["uniform"]["ess_per_s"]
+    net.close()
+    return out
+
+
 def cpu_baseline(k, n_sample):
     """The FP64 oracle as it stands, on the first n_sample configurations."""
     import numpy as np
@@ -224,6 +305,8 @@ def main():
     ap.add_argument("--no-mc", action="store_true", help="skip the Monte Carlo sweep timing")
     ap.add_argument("--no-spmm", action="store_true", help="skip the block SpMM bandwidth benchmark")
     ap.add_argument("--spmm-only", action="store_true", help="only the block SpMM bandwidth benchmark")
+    ap.add_argument("--no-ess", action="store_true", help="skip the learned vs uniform ESS measurement")
+    ap.add_argument("--ess-only", action="store_true", help="only the learned vs uniform ESS measurement")
     ap.add_argument("--seven", action="store_true", help="also time the 7-orbital mixed workload")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (3 times) and exit: the reference "
@@ -252,6 +335,9 @@ def main():
         return
     if a.spmm_only:
         print(json.dumps({"spmm_gated": measure_spmm(torch, hyb, I)}), flush=True)
+        return
+    if a.ess_only:
+        print(json.dumps({"ess": measure_ess(torch, hyb, I)}), flush=True)
         return
     r5 = measure_workload(1, a.steps, a.warmup, torch, hyb, I, dump=a.dump)
     # Roofline of the dominant kernel (the path kernel, one launch per batch with the
@@ -296,6 +382,8 @@ def main():
         line["detail"]["mc"] = measure_mc(torch, hyb, I)
     if not a.no_spmm:
         line["detail"]["spmm_gated"] = measure_spmm(torch, hyb, I)
+    if not a.no_ess:
+        line["detail"]["ess"] = measure_ess(torch, hyb, I)
     if not a.no_cpu:
         line["cpu_baseline"] = cpu_baseline(1, a.cpu_sample)
     print(json.dumps(line), flush=True)
