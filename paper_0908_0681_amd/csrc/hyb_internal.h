@@ -37,6 +37,12 @@ struct DeviceModel {
   float* ell_val32 = nullptr;
   int16_t* ell_perm = nullptr;  // [dim_b] per block: rows by descending length (ELL row i is row perm[i])
   int16_t* ell_len = nullptr;   // [dim_b] per block: length of ELL row i
+  // the same rows in natural order for the trace kernels, every block padded to the
+  // model-wide slot count tell_k: slot k of row r of block b at
+  // state_off_b * tell_k + k * dim_b + r
+  int16_t* tell_col = nullptr;
+  double* tell_val64 = nullptr;
+  float* tell_val32 = nullptr;
   // retained set
   int32_t* ret_block = nullptr; // [n_ret]
   double* ret_energy = nullptr; // [n_ret]
@@ -75,6 +81,7 @@ struct hyb_model {
   std::vector<double> ret_vec;
   // ELL layout of each block (built at upload): slots per row and offset of the block
   std::vector<int32_t> ell_k;
+  int32_t tell_k = 0;            // largest number of off-diagonal entries in a row
   std::vector<int64_t> ell_off;
   // device side
   bool uploaded = false;

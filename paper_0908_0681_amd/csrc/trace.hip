@@ -228,7 +228,7 @@ void free_device(hyb_model* m) {
   if (!m || !m->uploaded) return;
   DeviceModel& d = m->dev;
   void* ptrs[] = {d.states, d.rank, d.blocks, d.rowptr, d.col, d.val64, d.val32, d.diag64,
-                  d.ell_col, d.ell_val32, d.ell_perm, d.ell_len, d.ret_block, d.ret_energy, d.ret_off, d.ret_vec64, d.ret_vec32, d.ws};
+                  d.ell_col, d.ell_val32, d.ell_perm, d.ell_len, d.tell_col, d.tell_val64, d.tell_val32, d.ret_block, d.ret_energy, d.ret_off, d.ret_vec64, d.ret_vec32, d.ws};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   for (void*& e : m->events)
@@ -269,6 +269,10 @@ static TraceParams base_params(const hyb_model* m) {
   P.val64 = d.val64;
   P.val32 = d.val32;
   P.diag64 = d.diag64;
+  P.ecol = d.tell_col;
+  P.eval64 = d.tell_val64;
+  P.eval32 = d.tell_val32;
+  P.ek = m->tell_k;
   P.ret_block = d.ret_block;
   P.ret_energy = d.ret_energy;
   P.ret_off = d.ret_off;
@@ -445,6 +449,26 @@ int hyb_model_upload(hyb_model* m, void* stream) {
       }
     }
   }
+  // natural-order ELL for the trace kernels (padding: own index, value 0)
+  int kt = 0;
+  for (int g = 0; g < m->n_states; ++g) kt = std::max(kt, m->rowptr[g + 1] - m->rowptr[g]);
+  m->tell_k = kt;
+  const int64_t tell_total = std::max<int64_t>(int64_t(kt) * m->n_states, 1);
+  std::vector<int16_t> tell_col(tell_total, 0);
+  std::vector<double> tell_val(tell_total, 0.0);
+  std::vector<float> tell_val32(tell_total, 0.0f);
+  for (int b = 0; b < m->n_blocks; ++b) {
+    const BlockDev& B = m->blocks[b];
+    for (int r = 0; r < B.dim; ++r) {
+      const int g = B.state_off + r, n = m->rowptr[g + 1] - m->rowptr[g];
+      for (int k = 0; k < kt; ++k) {
+        const int64_t at = int64_t(B.state_off) * kt + int64_t(k) * B.dim + r;
+        tell_col[at] = int16_t(k < n ? m->col[m->rowptr[g] + k] : r);
+        tell_val[at] = k < n ? m->val[m->rowptr[g] + k] : 0.0;
+        tell_val32[at] = float(tell_val[at]);
+      }
+    }
+  }
   m->uploaded = true;  // so that free_device releases partial uploads
   if ((rc = dev_upload(d.states, m->states.data(), m->states.size(), s))) return rc;
   if ((rc = dev_upload(d.rank, m->rank.data(), m->rank.size(), s))) return rc;
@@ -458,6 +482,9 @@ int hyb_model_upload(hyb_model* m, void* stream) {
   if ((rc = dev_upload(d.ell_val32, ell_val.data(), ell_val.size(), s))) return rc;
   if ((rc = dev_upload(d.ell_perm, ell_perm.data(), ell_perm.size(), s))) return rc;
   if ((rc = dev_upload(d.ell_len, ell_len.data(), ell_len.size(), s))) return rc;
+  if ((rc = dev_upload(d.tell_col, tell_col.data(), tell_col.size(), s))) return rc;
+  if ((rc = dev_upload(d.tell_val64, tell_val.data(), tell_val.size(), s))) return rc;
+  if ((rc = dev_upload(d.tell_val32, tell_val32.data(), tell_val32.size(), s))) return rc;
   if ((rc = dev_upload(d.ret_block, m->ret_block.data(), m->ret_block.size(), s))) return rc;
   if ((rc = dev_upload(d.ret_energy, m->ret_energy.data(), m->ret_energy.size(), s))) return rc;
   if ((rc = dev_upload(d.ret_off, m->ret_off.data(), m->ret_off.size(), s))) return rc;

@@ -76,6 +76,12 @@ struct TraceParams {
   void* st_vec;        // two ping-pong vector buffers [2][n_pairs][vstride] of VT
   int32_t vstride;     // elements per path vector (>= largest block)
   double zero_tol2;    // an operator leaving less than this squared norm ends the path
+  // off-diagonal rows as padded ELL in natural order: slot k of row r of block b at
+  // state_off_b * ek + k * dim_b + r (padding: column r, value 0)
+  const int16_t* ecol;
+  const double* eval64;
+  const float* eval32;
+  int32_t ek;          // slots per row
 };
 
 __device__ __forceinline__ int64_t cfg_end(const TraceParams& P, int c) {
@@ -112,6 +118,25 @@ __device__ __forceinline__ double wave_sum(double x) {
   return (readlane_d(x, 0) + readlane_d(x, 16)) + (readlane_d(x, 32) + readlane_d(x, 48));
 }
 
+// 1/d to about one ulp: the hardware estimate refined by two Newton steps (d finite
+// and nonzero, far from the exponent range's ends).
+__device__ __forceinline__ double rcp_d(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  r = fma(r, fma(-d, r, 1.0), r);
+  return fma(r, fma(-d, r, 1.0), r);
+}
+
+// Root of y^2 - w y - s = 0 (s > 0) on the side right > 0 or right = false < 0,
+// without cancellation.
+__device__ __forceinline__ double pole_root(double w, double s, bool right) {
+  const double sq = sqrt(w * w + 4.0 * s);
+  if (right) return (w < 0.0) ? 2.0 * s / (sq - w) : 0.5 * (w + sq);
+  return (w > 0.0) ? -2.0 * s / (w + sq) : 0.5 * (w - sq);
+}
+
+// True on every lane when p holds on at least one lane of the wavefront.
+__device__ __forceinline__ bool wave_any(bool p) { return __builtin_amdgcn_ballot_w64(p) != 0; }
+
 template <typename VT>
 __device__ __forceinline__ double to_d(VT x) { return static_cast<double>(x); }
 
@@ -130,13 +155,28 @@ struct PathEngine {
   struct Small {
     double alpha[MAXM], beta[MAXM];  // Lanczos T_m
     double a[2][MAXM], b[2][MAXM];   // QR snapshot / output buffers
-    double q[MAXM * QLD];            // eigenvectors, row r = component r
-    int cur;                         // buffer holding the eigenvalues
+    double q[2][MAXM * QLD];         // eigenvectors, row r = component r (buffer qc)
+    double u[MAXM * QLD];            // eigenvectors of the arrowhead extension
+    double tho[MAXM], xr[MAXM];      // root j = tho[j] + xr[j] (origin pole, offset)
+    double zh[MAXM];                 // couplings recomputed from the roots
+    double tz[2 * MAXM];             // pole i: theta_i at 2i, z_i^2 at 2i + 1
+    double wk[MAXM];                 // exp(-tau (theta_i - theta_min)) Q[0][i]
+    int rank[MAXM];                  // sorting permutation after a QR solve
+    int cur;                         // buffer holding the eigenvalues (ascending)
+    int qc;                          // buffer holding the eigenvectors
   };
+  // Off-diagonal slots of each thread's rows held in LDS during a propagation, up to
+  // KL per row within a per-variant budget (rows with more entries use the CSR in HBM)
+  static constexpr int NR = NT * RPT;
+  static constexpr int SLAB_BYTES = (NT >= 512) ? 64 * 1024 : (NT >= 256) ? 96 * 1024 : 10 * 1024 * (NT / 64);
+  static constexpr int KL0 = SLAB_BYTES / (NR * int(sizeof(VT) + sizeof(int16_t)));
+  static constexpr int KL = KL0 > 16 ? 16 : KL0;
   struct Smem {
     VT vec[NT * RPT];
     double red[2][NW][NRED];
     Small small[NW];
+    VT sval[KL > 0 ? KL * NR : 1];       // slot q of local row r at q * NR + r
+    int16_t scol[KL > 0 ? KL * NR : 1];
   };
 
   const TraceParams& P;
@@ -199,7 +239,10 @@ struct PathEngine {
   __device__ __forceinline__ int row(int k) const { return tid + k * NT; }
 
   // y = (H_b - c_b) x for the rows owned by this thread.  x is staged in LDS.
-  __device__ __forceinline__ void spmv(const BlockDev& B, const VT (&x)[RPT], VT (&y)[RPT]) {
+  // y = (H_b - c_b) x.  The vector is shared through LDS; each thread's rows come
+  // from its own LDS slots when staged (stage_rows), else from the CSR in HBM.
+  __device__ __forceinline__ void spmv(const BlockDev& B, const VT (&x)[RPT], VT (&y)[RPT],
+                                       const double (&dg)[RPT], bool staged) {
 #pragma unroll
     for (int k = 0; k < RPT; ++k)
       if (row(k) < B.dim) S.vec[row(k)] = x[k];
@@ -208,16 +251,45 @@ struct PathEngine {
     for (int k = 0; k < RPT; ++k) {
       const int r = row(k);
       if (r < B.dim) {
-        const int g = B.state_off + r;
-        const int j0 = P.rowptr[g], j1 = P.rowptr[g + 1];
         VT acc = VT(0);
-        for (int j = j0; j < j1; ++j) acc += offval(j) * S.vec[P.col[j]];
-        y[k] = static_cast<VT>(P.diag64[g] * to_d(x[k]) + to_d(acc));
+        if (staged) {
+          const int K = P.ek;
+#pragma unroll 2
+          for (int q = 0; q < K; ++q) acc += S.sval[q * NR + r] * S.vec[S.scol[q * NR + r]];
+        } else {
+          const int g = B.state_off + r;
+          const int j0 = P.rowptr[g], j1 = P.rowptr[g + 1];
+          for (int j = j0; j < j1; ++j) acc += offval(j) * S.vec[P.col[j]];
+        }
+        y[k] = static_cast<VT>(dg[k] * to_d(x[k]) + to_d(acc));
       } else {
         y[k] = VT(0);
       }
     }
     __syncthreads();  // S.vec is rewritten by the next staging
+  }
+
+  // Loads the diagonal of this thread's rows of block B into registers and, when
+  // they fit, their off-diagonal ELL slots into this thread's LDS slots (read only
+  // by this thread, so no barrier is needed).  Returns whether the slots are staged.
+  __device__ __forceinline__ bool stage_rows(const BlockDev& B, double (&dg)[RPT]) {
+    const bool staged = P.ek <= KL;
+    const int K = P.ek;
+    const int64_t base = int64_t(B.state_off) * K;
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+      const int r = row(k);
+      dg[k] = (r < B.dim) ? P.diag64[B.state_off + r] : 0.0;
+      if (staged && r < B.dim) {
+        for (int q = 0; q < K; ++q) {
+          const int64_t at = base + int64_t(q) * B.dim + r;
+          if constexpr (sizeof(VT) == 8) S.sval[q * NR + r] = static_cast<VT>(P.eval64[at]);
+          else S.sval[q * NR + r] = static_cast<VT>(P.eval32[at]);
+          S.scol[q * NR + r] = P.ecol[at];
+        }
+      }
+    }
+    return staged;
   }
 
   // x <- O x with O = c_f (dagger 0) or c_f^dag (dagger 1), block B -> Bt.
@@ -251,13 +323,12 @@ struct PathEngine {
     return block_sum1(nrm);
   }
 
-  // Eigendecomposition of the m x m symmetric tridiagonal T = (alpha, beta) of this
-  // wave by implicit QR sweeps with the Wilkinson shift (the host eigensolver's
-  // algorithm).  Every lane reads the same snapshot of T (buffer `in`) and takes the
-  // same decisions; lane 0 writes the swept T into the other buffer, which becomes
-  // the snapshot after a wave synchronisation, so no lane ever reads an entry while
-  // another writes it.  Lane r (< m) keeps row r of the eigenvector matrix in W.q.
-  // On return the eigenvalues are in W.a[W.cur][0..m).  Returns the sweep count.
+  // Eigendecomposition of the m x m symmetric tridiagonal T_m = (alpha, beta) of this
+  // wave, called for m = 1, 2, 3, ... as the Lanczos recursion grows T.  On return
+  // the eigenvalues are in ascending order in W.a[W.cur][0..m) and lane r (< m) has
+  // row r of the eigenvector matrix in W.q.  From m = 3 on, the decomposition of
+  // T_{m-1} is extended by one row and column (extend_eig); where that is not safe,
+  // T_m is solved from scratch by QR and the result sorted.  Returns a work count.
   __device__ int small_eig(Small& W, int m) {
     if (m <= 2) {
       // closed forms: no sweep needed for the first two Lanczos steps
@@ -299,19 +370,296 @@ struct PathEngine {
       if (lane == 0) {
         W.a[0][0] = l0;
         W.a[0][1] = l1;
-        W.q[0] = q00;
-        W.q[1] = q01;
-        W.q[QLD] = q10;
-        W.q[QLD + 1] = q11;
+        W.q[0][0] = q00;
+        W.q[0][1] = q01;
+        W.q[0][QLD] = q10;
+        W.q[0][QLD + 1] = q11;
         W.cur = 0;
+        W.qc = 0;
       }
       wave_sync();
       return 0;
     }
+    if (extend_eig(W, m)) return 1;
+    const int sweeps = qr_eig(W, m);
+    sort_eig(W, m);
+    return sweeps + 1;
+  }
+
+  // Rank-one extension.  In the basis of T_{m-1}'s eigenvectors plus the new Lanczos
+  // vector, T_m is an arrowhead matrix: the poles theta_0 < ... < theta_{n-1}
+  // (n = m - 1) and alpha_{m-1} on the diagonal, the couplings z_i = beta_{m-2}
+  // Q[m-2][i] in the last row and column.  Its eigenvalues are the roots of
+  //   h(lam) = alpha_{m-1} - lam - sum_i z_i^2 / (theta_i - lam),
+  // which decreases between poles: one root below theta_0, one between each pair of
+  // neighbouring poles, one above theta_{n-1}.  Lane k finds root k as an offset x
+  // from its nearer pole (so that roots close to a pole keep their relative
+  // accuracy) by steps on a rational model of h, bracketed by bisection.  The
+  // couplings are then recomputed from the computed roots with Loewner's formula,
+  // which makes the roots exact for a nearby arrowhead and the eigenvectors
+  // orthogonal to working precision (Gu and Eisenstat); eigenvector k is
+  // (z_i / (lam_k - theta_i), 1) normalised, and Q_m = diag(Q_{m-1}, 1) U.
+  // Returns false, before anything the QR path reads has changed, when a coupling or
+  // a pole gap is negligible against ||T_m|| or an iteration does not settle.
+  __device__ bool extend_eig(Small& W, int m) {
+    constexpr int NP = MAXM - 1;  // most poles
+    const int n = m - 1, cur = W.cur, qc = W.qc;
+    const double* th = W.a[cur];
+    const double* Q = W.q[qc];
+    const double eps = 2.220446049250313e-16;
+    const double bc = W.beta[m - 2], alpha = W.alpha[m - 1];
+    const double tnorm = fmax(fabs(th[0]), fabs(th[n - 1])) + fabs(alpha) + bc;
+    const double tiny = 64.0 * eps * tnorm;
+    // lane i < n: pole i and its squared coupling into LDS; negligible couplings or
+    // pole gaps end the attempt
+    bool bad = !(tnorm < 1e300);
+    if (lane < n) {
+      const double ti = th[lane], zi = bc * Q[(m - 2) * QLD + lane];
+      W.tz[2 * lane] = ti;
+      W.tz[2 * lane + 1] = zi * zi;
+      if (!(zi * zi > tiny * tiny)) bad = true;
+      if (lane + 1 < n && !(th[lane + 1] - ti > tiny)) bad = true;
+    }
+    if (wave_any(bad)) return false;
+    wave_sync();
+
+    // h and the parts of -h' from poles left (dl_sum) and right (dr_sum) of root k,
+    // at lam = tho + x; sabs = sum of |z_i^2 / (theta_i - lam)|
+    auto eval = [&](int k, double tho, double x, double& dl_sum, double& dr_sum, double& sabs) {
+      double sum = 0.0;
+      dl_sum = 0.0;
+      dr_sum = 0.0;
+      sabs = 0.0;
+#pragma unroll 2
+      for (int i = 0; i < n; ++i) {
+        const double r = rcp_d((W.tz[2 * i] - tho) - x);
+        const double ti = W.tz[2 * i + 1] * r;
+        sum += ti;
+        if (i < k) dl_sum += ti * r;
+        else dr_sum += ti * r;
+        sabs += fabs(ti);
+      }
+      return (alpha - tho) - x - sum;
+    };
+
+    double tho = 0.0, x = 0.0;
+    bool conv = true;
+    if (lane < m) {
+      const int k = lane;
+      double lo, hi, h, dls, drs, sabs;
+      double DL = 0.0, DR = 0.0;  // poles bracketing an interior root, relative to tho
+      const bool interior = (k > 0 && k < n);
+      const double tl = (k > 0) ? th[k - 1] : 0.0, tr = (k < n) ? th[k] : 0.0;
+      int o;  // origin pole
+      if (interior) {
+        const double g = tr - tl;
+        h = eval(k, tl, 0.5 * g, dls, drs, sabs);
+        if (h > 0.0) {  // root in the right half: origin at theta_k
+          o = k;
+          tho = tr;
+          x = -0.5 * g;
+          lo = x;
+          hi = 0.0;
+          DL = -g;
+        } else {
+          o = k - 1;
+          tho = tl;
+          x = 0.5 * g;
+          lo = 0.0;
+          hi = x;
+          DR = g;
+        }
+      } else {
+        o = (k == 0) ? 0 : n - 1;
+        tho = (k == 0) ? tr : tl;
+        const double A0 = alpha - tho;
+        double zn2 = 0.0;
+        for (int i = 0; i < n; ++i) zn2 += W.tz[2 * i + 1];
+        const double zn = sqrt(zn2);
+        lo = (k == 0) ? 2.0 * (fmin(0.0, A0) - zn) : 0.0;  // Weyl bounds
+        hi = (k == 0) ? 0.0 : 2.0 * (fmax(0.0, A0) + zn);
+      }
+      // start from the root of the model that keeps the linear term and the origin
+      // pole and freezes the other poles at lam = theta_o
+      {
+        double a = 0.0;
+#pragma unroll 2
+        for (int i = 0; i < n; ++i)
+          if (i != o) a += W.tz[2 * i + 1] * rcp_d(W.tz[2 * i] - tho);
+        const double xp = pole_root((alpha - tho) - a, W.tz[2 * o + 1], k > o);
+        if (xp > lo && xp < hi) x = xp;
+        else if (!interior) x = 0.5 * (lo + hi);
+        if (x == xp || !interior) h = eval(k, tho, x, dls, drs, sabs);
+      }
+      conv = false;
+      for (int it = 0; it < 60; ++it) {
+        if (!(h == h)) break;
+        if (h > 0.0) lo = x;
+        else hi = x;
+        const double A0 = alpha - tho, hp = 1.0 + dls + drs;
+        const double errb = eps * (8.0 * sabs + 4.0 * fabs(A0) + 4.0 * fabs(x) + 2.0 * fabs(x) * hp);
+        if (fabs(h) <= errb || hi - lo <= 4.0 * eps * fmax(fabs(lo), fabs(hi))) {
+          conv = true;
+          break;
+        }
+        // one-pole model: the exact linear term and the origin pole carrying all of
+        // the poles' part of -h' (the whole step for an outer root)
+        const double s1 = (dls + drs) * x * x;
+        const double a1 = ((alpha - tho) - x - h) + (dls + drs) * x;
+        double xn = pole_root(A0 - a1, s1, x > 0.0);
+        if (interior) {
+          // two-pole model: the linear term, and the bracketing poles carrying the
+          // poles' part of -h' of their side; a few Newton steps from the one-pole root
+          const double dl = DL - x, dr = DR - x;
+          const double sL = dls * dl * dl, sR = drs * dr * dr;
+          const double c = h + x + dls * dl + drs * dr;
+          double y = (xn > lo && xn < hi) ? xn : x;
+          for (int q = 0; q < 3; ++q) {
+            const double rl = rcp_d(DL - y), rr = rcp_d(DR - y);
+            const double f = c - y - sL * rl - sR * rr;
+            const double fp = -1.0 - sL * rl * rl - sR * rr * rr;
+            const double y2 = y - f * rcp_d(fp);
+            if (!(y2 > lo && y2 < hi)) break;
+            y = y2;
+          }
+          xn = y;
+        }
+        const bool bis = !(xn > lo && xn < hi);
+        if (bis) xn = 0.5 * (lo + hi);
+        if (xn == x) {
+          conv = true;
+          break;
+        }
+        // a model step this small leaves an error far below rounding: take it
+        if (!bis && fabs(xn - x) <= 0x1p-30 * fabs(xn)) {
+          x = xn;
+          conv = true;
+          break;
+        }
+        x = xn;
+        h = eval(k, tho, x, dls, drs, sabs);
+      }
+      W.tho[k] = tho;
+      W.xr[k] = x;
+      W.a[cur ^ 1][k] = tho + x;
+    }
+    if (wave_any(!conv)) return false;
+    wave_sync();
+
+    // Loewner: zh_i^2 = -prod_j (lam_j - theta_i) / prod_{l != i} (theta_l - theta_i),
+    // as a product of interlaced ratios (each of order one, so no overflow)
+    bool okz = true;
+    if (lane < n) {
+      const int i = lane;
+      const double ti = W.tz[2 * i];
+      double f[MAXM];
+#pragma unroll
+      for (int j = 0; j < MAXM; ++j) {
+        f[j] = 1.0;
+        if (j < m) {
+          const double dj = (W.tho[j] - ti) + W.xr[j];
+          // denominator pole of factor j: theta_j left of i, theta_{j-1} right of i+1
+          if (j < i) f[j] = dj * rcp_d(W.tz[2 * j] - ti);
+          else if (j > i + 1) f[j] = dj * rcp_d(W.tz[2 * (j - 1)] - ti);
+          else f[j] = dj;
+        }
+      }
+#pragma unroll
+      for (int st = 1; st < MAXM; st *= 2)
+#pragma unroll
+        for (int j = 0; j + st < MAXM; j += 2 * st) f[j] *= f[j + st];
+      const double pr = f[0];
+      okz = (pr < 0.0) && (pr > -1e300);
+      W.zh[i] = copysign(sqrt(fabs(pr)), Q[(m - 2) * QLD + i]);
+    }
+    if (wave_any(!okz)) return false;
+    wave_sync();
+
+    // eigenvector k of the arrowhead into column k of U
+    bool oku = true;
+    if (lane < m) {
+      double nrm = 1.0;
+#pragma unroll
+      for (int i = 0; i < NP; ++i) {
+        if (i < n) {
+          const double ui = W.zh[i] * rcp_d((tho - W.tz[2 * i]) + x);
+          W.u[i * QLD + lane] = ui;
+          nrm += ui * ui;
+        }
+      }
+      oku = (nrm < 1e300);
+      const double inv = rcp_d(sqrt(nrm));
+#pragma unroll
+      for (int i = 0; i < NP; ++i)
+        if (i < n) W.u[i * QLD + lane] *= inv;
+      W.u[n * QLD + lane] = inv;
+    }
+    if (wave_any(!oku)) return false;
+    wave_sync();
+
+    // Q_m = diag(Q_{m-1}, 1) U into the other buffer, entries (r, j) spread over lanes
+    double* Qn = W.q[qc ^ 1];
+    for (int p0 = 0; p0 < 16 * m; p0 += 64) {
+      const int pair = p0 + lane, r = pair >> 4, j = pair & 15;
+      if (r < m && j < m) {
+        double acc;
+        if (r < n) {
+          acc = 0.0;
+#pragma unroll
+          for (int i = 0; i < NP; ++i)
+            if (i < n) acc += Q[r * QLD + i] * W.u[i * QLD + j];
+        } else {
+          acc = W.u[n * QLD + j];
+        }
+        Qn[r * QLD + j] = acc;
+      }
+    }
+    wave_sync();
+    if (lane == 0) {
+      W.cur = cur ^ 1;
+      W.qc = qc ^ 1;
+    }
+    wave_sync();
+    return true;
+  }
+
+  // Sorts the eigenpairs of a QR solve into ascending order (ties by index).
+  __device__ void sort_eig(Small& W, int m) {
+    const int cur = W.cur;
+    const double* th = W.a[cur];
+    if (lane < m) {
+      const double v = th[lane];
+      int r = 0;
+      for (int j = 0; j < m; ++j) r += (th[j] < v || (th[j] == v && j < lane)) ? 1 : 0;
+      W.rank[lane] = r;
+      W.a[cur ^ 1][r] = v;
+    }
+    wave_sync();
+    if (lane < m) {
+      double row[MAXM];
+      double* Q = W.q[W.qc];
+#pragma unroll
+      for (int c = 0; c < MAXM; ++c) row[c] = (c < m) ? Q[lane * QLD + c] : 0.0;
+#pragma unroll
+      for (int c = 0; c < MAXM; ++c)
+        if (c < m) Q[lane * QLD + W.rank[c]] = row[c];
+    }
+    wave_sync();
+    if (lane == 0) W.cur = cur ^ 1;
+    wave_sync();
+  }
+
+  // Implicit QR sweeps with the Wilkinson shift on T_m from scratch (the host
+  // eigensolver's algorithm).  Every lane reads the same snapshot of T (buffer `in`)
+  // and takes the same decisions; lane 0 writes the swept T into the other buffer,
+  // which becomes the snapshot after a wave synchronisation, so no lane ever reads an
+  // entry while another writes it.  Lane r (< m) keeps row r of the eigenvector
+  // matrix in W.q.  Eigenvalues in W.a[W.cur][0..m), unsorted.  Returns the sweeps.
+  __device__ int qr_eig(Small& W, int m) {
     if (lane < m) {
       W.a[0][lane] = W.alpha[lane];
       W.b[0][lane] = (lane + 1 < m) ? W.beta[lane] : 0.0;
-      for (int c = 0; c < m; ++c) W.q[lane * QLD + c] = (c == lane) ? 1.0 : 0.0;
+      for (int c = 0; c < m; ++c) W.q[W.qc][lane * QLD + c] = (c == lane) ? 1.0 : 0.0;
     }
     int in = 0;
     wave_sync();
@@ -364,7 +712,7 @@ struct PathEngine {
           if (k + 1 < q) W.b[out][k + 1] = nb1;
         }
         if (lane < m) {
-          double* qr = &W.q[lane * QLD];
+          double* qr = &W.q[W.qc][lane * QLD];
           const double qk = qr[k], qk1 = qr[k + 1];
           qr[k] = c * qk + s * qk1;
           qr[k + 1] = -s * qk + c * qk1;
@@ -391,6 +739,8 @@ struct PathEngine {
     const int kmax = (P.kmax < MAXM) ? P.kmax : MAXM;
     const double shift = B.shift - P.E0;  // H - E0 = (H - c_b) + (c_b - E0)
     constexpr double EPSV = (sizeof(VT) == 8) ? 2.220446049250313e-16 : 5.9604644775390625e-08;
+    double dg[RPT];
+    const bool staged = stage_rows(B, dg);
     double remaining = dtau;
     VT V[MAXM + 1][RPT];
     for (int nsub = 0; remaining > 0.0; ++nsub) {
@@ -412,7 +762,7 @@ struct PathEngine {
 #pragma unroll
             for (int k = 0; k < RPT; ++k) vj[k] = V[i][k];
           }
-        spmv(B, vj, w);
+        spmv(B, vj, w, dg, staged);
         // classical Gram-Schmidt twice against V_0..V_j; the second round also
         // reduces ||w||^2 so that beta_j needs no extra round
         double hj;
@@ -496,23 +846,24 @@ struct PathEngine {
           atomicOr(&P.counters[2], ERR_NOCONV);
           return false;
         }
+        // eigenvalues ascend, so theta_0 is the smallest; lane i (<= j) takes the
+        // term of eigenpair i: w_i = exp(-tau (theta_i - theta_0)) Q[0][i], with
+        // ||y||^2 = sum_i w_i^2 and y_j = sum_i Q[j][i] w_i
         const double* theta = W.a[W.cur];
+        const double* Q = W.q[W.qc];
         theta_min = theta[0];
-        for (int i = 1; i <= j; ++i) theta_min = fmin(theta_min, theta[i]);
+        const double dth = (lane <= j) ? theta[lane] - theta_min : 0.0;
+        const double q0 = (lane <= j) ? Q[lane] : 0.0;
+        const double qj = (lane <= j) ? Q[j * QLD + lane] : 0.0;
         const double breakdown = 4.0 * EPSV * (tscale + 1e-300);
         const bool last = (j + 1 >= kmax);
         double tau_try = remaining;
         bool ok = false;
-        double ylane = 0.0;
+        double wl = 0.0;
         for (int attempt = 0; attempt < 60; ++attempt) {
-          double yn2 = 0.0;
-          ylane = 0.0;
-          for (int i = 0; i <= j; ++i) {
-            const double wk = exp(-tau_try * (theta[i] - theta_min)) * W.q[i];  // Q[0][i]
-            yn2 += wk * wk;
-            if (lane <= j) ylane += W.q[lane * QLD + i] * wk;
-          }
-          const double ylast = readlane_d(ylane, j);
+          wl = exp(-tau_try * dth) * q0;
+          const double yn2 = wave_sum(wl * wl);
+          const double ylast = wave_sum(qj * wl);
           ynorm = sqrt(yn2);
           const double est = bj * fabs(ylast) / ynorm;
           ok = (est <= P.tol) || (bj <= breakdown);
@@ -520,9 +871,14 @@ struct PathEngine {
           tau_try *= 0.5;  // depth cap reached: shorten the substep
         }
         if (ok) {
+          // y = Q w: lane r (<= j) gets component r
+          if (lane <= j) W.wk[lane] = wl;
+          wave_sync();
+          double yr = 0.0;
+          for (int i = 0; i <= j; ++i) yr += Q[(lane <= j ? lane : 0) * QLD + i] * W.wk[i];
           m = j + 1;
           tau_used = tau_try;
-          yv = ylane;
+          yv = (lane <= j) ? yr : 0.0;
           break;
         }
         if (last) {
