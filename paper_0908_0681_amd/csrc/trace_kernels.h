@@ -18,6 +18,7 @@
 
 #include <hip/hip_runtime.h>
 #include <cstdint>
+#include <type_traits>
 
 #include "hyb_internal.h"
 
@@ -103,6 +104,11 @@ __device__ __forceinline__ double dpp_d(double v) {
   return __hiloint2double(hi, lo);
 }
 
+__device__ __forceinline__ double shfl_xor_d(double v, int mask) {
+  const int lo = __shfl_xor(__double2loint(v), mask), hi = __shfl_xor(__double2hiint(v), mask);
+  return __hiloint2double(hi, lo);
+}
+
 __device__ __forceinline__ double readlane_d(double v, int lane) {
   int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
   int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
@@ -116,6 +122,56 @@ __device__ __forceinline__ double wave_sum(double x) {
   x += dpp_d<0x141>(x);  // row_half_mirror
   x += dpp_d<0x140>(x);  // row_mirror: every lane holds its 16-lane row sum
   return (readlane_d(x, 0) + readlane_d(x, 16)) + (readlane_d(x, 32) + readlane_d(x, 48));
+}
+
+// Wave totals of NV values per lane (NV = 4, 8 or 16): every lane receives all of
+// them, bitwise identical across lanes.  A reduce-scatter inside each 16-lane row
+// first: at each step a lane pairs with a partner (rotate by 8, mirror within 8,
+// swap pairs, swap neighbours), keeps half of its values and adds the partner's copy
+// of that half, so after log2(NV) steps each lane holds one value summed over
+// NV lanes; the rest of its row and the four rows are then summed with two DPP and
+// two cross-row exchanges, and each total is read from a lane that holds it.  About
+// half the instructions of NV separate wave sums.
+template <int NV>
+__device__ __forceinline__ void wave_sums(double* v) {
+  static_assert(NV == 4 || NV == 8 || NV == 16, "NV is 4, 8 or 16");
+  const int lane = threadIdx.x & 63;
+  double a[NV];
+#pragma unroll
+  for (int q = 0; q < NV; ++q) a[q] = v[q];
+  // step s keeps the upper half on lanes with bit (8 >> s) set
+  auto step = [&](auto ctrl_tag, int bit, int n) {
+    constexpr int CTRL = decltype(ctrl_tag)::value;
+    const bool upper = (lane & bit) != 0;
+#pragma unroll
+    for (int q = 0; q < NV / 2; ++q) {
+      if (q < n) {
+        const double send = upper ? a[q] : a[q + n];
+        const double keep = upper ? a[q + n] : a[q];
+        a[q] = keep + dpp_d<CTRL>(send);
+      }
+    }
+  };
+  step(std::integral_constant<int, 0x128>{}, 8, NV / 2);  // row_ror:8 (lane ^ 8)
+  step(std::integral_constant<int, 0x141>{}, 4, NV / 4);  // row_half_mirror (bit 2 differs)
+  if constexpr (NV >= 8) step(std::integral_constant<int, 0x4E>{}, 2, NV / 8);  // lane ^ 2
+  if constexpr (NV >= 16) step(std::integral_constant<int, 0xB1>{}, 1, NV / 16);  // lane ^ 1
+  double x = a[0];
+  if constexpr (NV < 8) x += dpp_d<0x4E>(x);
+  if constexpr (NV < 16) x += dpp_d<0xB1>(x);
+  // the four rows
+  x += shfl_xor_d(x, 16);
+  x += shfl_xor_d(x, 32);
+  // value c sits on the lane whose bits 3, 2, 1, 0 spell c from its top bit down
+  constexpr int S = (NV == 4) ? 2 : (NV == 8) ? 3 : 4;
+#pragma unroll
+  for (int c = 0; c < NV; ++c) {
+    int l = 0;
+#pragma unroll
+    for (int t = 0; t < S; ++t)
+      if ((c >> (S - 1 - t)) & 1) l |= (8 >> t);
+    v[c] = readlane_d(x, l);
+  }
 }
 
 // 1/d to about one ulp: the hardware estimate refined by two Newton steps (d finite
@@ -147,7 +203,7 @@ __device__ __forceinline__ double to_d(VT x) { return static_cast<double>(x); }
 template <typename VT, int NT, int RPT, int MAXM>
 struct PathEngine {
   static constexpr int NW = NT / 64;
-  static constexpr int NRED = MAXM + 2;  // partial sums per reduction round
+  static constexpr int NRED = (MAXM + 2 > 16) ? MAXM + 2 : 16;  // partial sums per reduction round
   static constexpr int QLD = MAXM + 1;   // padded row length of Q in LDS
 
   // Tridiagonal work space of one wavefront (uniform values; every wave of the
@@ -207,9 +263,16 @@ struct PathEngine {
   // in a fixed summation order.
   template <int K>
   __device__ __forceinline__ void block_sum(double (&v)[K], int kact) {
+    if (kact <= 2 || kact > 16 || K < 16) {
 #pragma unroll
-    for (int k = 0; k < K; ++k)
-      if (k < kact) v[k] = wave_sum(v[k]);
+      for (int k = 0; k < K; ++k)
+        if (k < kact) v[k] = wave_sum(v[k]);
+    } else if constexpr (K >= 16) {
+      // several values at once, in place (entries from kact up are zero on entry)
+      if (kact <= 4) wave_sums<4>(v);
+      else if (kact <= 8) wave_sums<8>(v);
+      else wave_sums<16>(v);
+    }
     if constexpr (NW > 1) {
       if (lane == 0) {
 #pragma unroll
