@@ -336,19 +336,38 @@ struct PathEngine {
   // they fit, their off-diagonal ELL slots into this thread's LDS slots (read only
   // by this thread, so no barrier is needed).  Returns whether the slots are staged.
   __device__ __forceinline__ bool stage_rows(const BlockDev& B, double (&dg)[RPT]) {
-    const bool staged = P.ek <= KL;
     const int K = P.ek;
+    const bool staged = K <= KL;
     const int64_t base = int64_t(B.state_off) * K;
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
       const int r = row(k);
       dg[k] = (r < B.dim) ? P.diag64[B.state_off + r] : 0.0;
-      if (staged && r < B.dim) {
-        for (int q = 0; q < K; ++q) {
-          const int64_t at = base + int64_t(q) * B.dim + r;
-          if constexpr (sizeof(VT) == 8) S.sval[q * NR + r] = static_cast<VT>(P.eval64[at]);
-          else S.sval[q * NR + r] = static_cast<VT>(P.eval32[at]);
-          S.scol[q * NR + r] = P.ecol[at];
+    }
+#pragma unroll 1
+    for (int k = 0; k < RPT; ++k) {
+      const int r = row(k);
+      const bool in = r < B.dim;
+      if constexpr (KL > 0) {
+        if (staged && in && K > 0) {
+          // every slot of the row is requested before the first LDS store (slots past
+          // K re-read slot K - 1 of the same row and are not stored), so the loads
+          // are in flight together
+          VT vv[KL];
+          int16_t cc[KL];
+#pragma unroll
+          for (int q = 0; q < KL; ++q) {
+            const int64_t at = base + int64_t(q < K ? q : K - 1) * B.dim + r;
+            if constexpr (sizeof(VT) == 8) vv[q] = static_cast<VT>(P.eval64[at]);
+            else vv[q] = static_cast<VT>(P.eval32[at]);
+            cc[q] = P.ecol[at];
+          }
+#pragma unroll
+          for (int q = 0; q < KL; ++q)
+            if (q < K) {
+              S.sval[q * NR + r] = vv[q];
+              S.scol[q * NR + r] = cc[q];
+            }
         }
       }
     }
