@@ -96,12 +96,45 @@ def measure_workload(k, steps, warmup, torch, hyb, I, dump=""):
         path_bytes=(2.0 * rowsteps + 2.0 * rows) * vsize,
     )
     res["mean_krylov_depth"] = steps_total / max(1, sum_intervals(batch, out, torch))
+    res["substeps"] = int(out["substeps"].clamp(min=0).sum().item())
+    res["depth_histogram"] = depth_histogram(batch, out)
+    # the same batch handed over in host memory: configurations copied in and the
+    # results copied out on the stream (PCIe-inclusive; never the headline value)
+    for _ in range(2):
+        model.trace_batch(batch)
+    torch.cuda.synchronize()
+    hs = []
+    for _ in range(5):
+        t1 = time.perf_counter()
+        model.trace_batch(batch)
+        torch.cuda.synchronize()
+        hs.append(time.perf_counter() - t1)
+    hs.sort()
+    res["host_buffers"] = {"traces_per_s": batch.n_configs / hs[len(hs) // 2], "ms": 1e3 * hs[len(hs) // 2],
+                           "note": "hyb_trace_batch with host arrays, median of 5, wall clock"}
     if dump:
         import numpy as np
         np.savez(dump, krylov_steps=out["krylov_steps"].cpu().numpy(), substeps=out["substeps"].cpu().numpy(),
                  feasible_paths=out["feasible_paths"].cpu().numpy(), rowsteps=out["rowsteps"].cpu().numpy(),
                  n_ops=np.diff(batch.offsets))
     return res
+
+
+def depth_histogram(batch, out):
+    """Configurations by their mean Krylov depth per propagated interval (Lanczos steps
+    over feasible paths x intervals), in unit bins; the kernels record per-configuration
+    totals, not per-interval depths."""
+    import numpy as np
+    nops = np.diff(batch.offsets)
+    feas = out["feasible_paths"].cpu().numpy()
+    steps = out["krylov_steps"].cpu().numpy()
+    n_int = feas * np.maximum(nops - 1, 0)
+    ok = n_int > 0
+    depth = steps[ok] / n_int[ok]
+    edges = np.arange(0, 13)
+    h, _ = np.histogram(np.minimum(depth, 12 - 1e-9), bins=edges)
+    return {"bins": [f"[{a},{a + 1})" for a in edges[:-1]], "configs": h.tolist(),
+            "kind": "per-configuration mean depth"}
 
 
 def sum_intervals(batch, out, torch):
@@ -290,7 +323,17 @@ def cpu_baseline(k, n_sample):
     t0 = time.perf_counter()
     o.trace_batch(b)
     dt = time.perf_counter() - t0
+    cpu = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    cpu = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {"value": n_sample / dt, "unit": "traces/s", "cores": int(threads), "kind": "oracle",
+            "per_core": n_sample / dt / max(1, int(threads)), "cpu": cpu, "os_cpu_count": os.cpu_count(),
             "sample": f"first {n_sample} of the {w.n_configs} configurations of {w.name} "
                       f"({dt:.1f} s; model setup {setup:.1f} s not counted)"}
 
@@ -300,14 +343,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--cpu-sample", type=int, default=192)
+    ap.add_argument("--cpu-sample", type=int, default=1024)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-mc", action="store_true", help="skip the Monte Carlo sweep timing")
     ap.add_argument("--no-spmm", action="store_true", help="skip the block SpMM bandwidth benchmark")
     ap.add_argument("--spmm-only", action="store_true", help="only the block SpMM bandwidth benchmark")
     ap.add_argument("--no-ess", action="store_true", help="skip the learned vs uniform ESS measurement")
     ap.add_argument("--ess-only", action="store_true", help="only the learned vs uniform ESS measurement")
-    ap.add_argument("--seven", action="store_true", help="also time the 7-orbital mixed workload")
+    ap.add_argument("--no-seven", action="store_true", help="skip the 7-orbital mixed workload")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (3 times) and exit: the reference "
                          "for scaling hardware byte counters")
@@ -371,13 +414,14 @@ def main():
                      "note": "latency-bound: per-path Lanczos recurrences on <=100-row blocks"},
         "detail": {k: r5[k] for k in ("prop_launches", "prop_ms", "op_launches", "op_ms", "scan_ms",
                                       "steps_ms", "reduce_ms", "lanczos_steps", "mean_krylov_depth",
-                                      "feasible_paths", "path_bytes")},
+                                      "substeps", "depth_histogram", "feasible_paths", "path_bytes",
+                                      "host_buffers")},
     }
-    if a.seven:
+    if not a.no_seven:
         r7 = measure_workload(2, max(2, a.steps // 5), 1, torch, hyb, I)
         line["detail"]["kanamori-7orb-b40"] = {k: r7[k] for k in (
             "traces_per_s", "ms_per_step", "prop_ms", "prop_launches", "prop_bytes", "mean_krylov_depth",
-            "feasible_paths")}
+            "substeps", "feasible_paths", "host_buffers")}
     if not a.no_mc:
         line["detail"]["mc"] = measure_mc(torch, hyb, I)
     if not a.no_spmm:
