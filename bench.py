@@ -231,14 +231,70 @@ def _g_half(mc, beta, n_tau):
     return G[:, :, n_tau // 2 - 1:n_tau // 2 + 1].mean(axis=(1, 2)), nm
 
 
-def measure_ess(torch, hyb, I, therm=2000, harvests=100, train_steps=1000, moves=1000, n_tau=20):
+def _sg_half(g, nm, beta, n_tau):
+    """Per chain: the sign-weighted measurement s*G at beta/2 (flavor average of the
+    two bins) averaged over nm measurements; no division by the sign sum, so chains
+    with small sign sums do not blow up."""
+    import numpy as np
+    n = np.maximum(np.asarray(nm, dtype=np.float64), 1.0).reshape(-1, 1, 1)
+    SG = -g / (beta * (beta / n_tau) * n)
+    return SG[:, :, n_tau // 2 - 1:n_tau // 2 + 1].mean(axis=(1, 2))
+
+
+def _g_blocks(mc, beta, n_tau, n_blocks, moves):
+    """Per chain and block: the mean of s*G(beta/2) over each block of moves / n_blocks
+    moves, and the chains' totals of s*G and s over all blocks."""
+    import numpy as np
+    per = moves // n_blocks
+    out = []
+    g0, ms0, nm0 = mc.accumulators()
+    gs, ms_start = g0, ms0
+    for bi in range(n_blocks):
+        mc.sweep(per)
+        if per >= 500:
+            print(f"[ess] block {bi + 1}/{n_blocks} of {per} moves", file=sys.stderr, flush=True)
+        g1, ms1, nm1 = mc.accumulators()
+        out.append(_sg_half(g1 - g0, nm1 - nm0, beta, n_tau))
+        g0, ms0, nm0 = g1, ms1, nm1
+    return np.stack(out, axis=1), _sg_half(g0 - gs, 1, beta, n_tau), ms0 - ms_start
+
+
+def _thermalise(mc, chunk=1000, min_moves=10000, max_moves=40000, rtol=0.003):
+    """Uniform sweeps until the mean expansion order over the chains changes by less
+    than rtol between consecutive chunks (the chains start at orders spread over
+    0..200, far from equilibrium).  Returns the moves spent and the last mean order."""
+    import numpy as np
+    done, prev = 0, None
+    while done < max_moves:
+        mc.sweep(chunk)
+        done += chunk
+        order = float(np.mean(mc.state()["k"].sum(axis=1)))
+        print(f"[ess] thermalising: {done} moves, mean order {order:.2f}", file=sys.stderr, flush=True)
+        if done >= min_moves and prev is not None and abs(order - prev) <= rtol * max(prev, 1.0):
+            break
+        prev = order
+    return done, order
+
+
+def measure_ess(torch, hyb, I, harvests=100, train_steps=1000, moves=20000, n_tau=20, eps=0.1,
+                n_blocks=20, snapshots=4, seed_offset=0):
     """Effective samples per second of G(beta/2), learned vs uniform insertion, on the
     5-orbital model with the semicircular bath (256 chains).  Both samplers start from
-    the same thermalised uniform-sampler state.  ESS = n_chains * var(one measurement)
-    / var(chain mean) (chains are independent; the single-measurement variance is
-    taken across chains at one measurement); wall time includes the network's
-    inference.  The network is trained beforehand on pairs harvested from the uniform
-    chains (time reported separately)."""
+    the same thermalised uniform-sampler state.  ESS = n_chains * var1 / var(chain mean),
+    with var1 the variance of a single measurement (one move), pooled over snapshots
+    of both samplers (a property of the distribution, not of the sampler), and
+    var(chain mean) estimated two ways:
+    - across chains: the variance of the 256 chain means (the only estimate for runs
+      not much longer than the autocorrelation time, noisy at the 10-20% level and
+      inflated by the shared starting states);
+    - blocking: the run as n_blocks blocks, var(block means) / n_blocks per chain,
+      averaged over chains (valid once a block is much longer than the
+      autocorrelation time).
+    The observable is the sign-weighted measurement s*G(beta/2) (G = <sG>/<s>, reported
+    as the pooled ratio over all chains).  Both samplers start from the same
+    uniform-sampler state, thermalised until the mean expansion order is stationary.  Wall time includes the network's inference.  The
+    network is trained beforehand on pairs harvested from the uniform chains (time
+    reported separately)."""
     import numpy as np
     setup = I.mc_setup(3)
     w = setup.workload
@@ -249,9 +305,9 @@ def measure_ess(torch, hyb, I, therm=2000, harvests=100, train_steps=1000, moves
     chains = I.mc_initial_configs(setup)
     r = m.trace_batch(I.from_lists([I.mc_merged(cre, ann) for cre, ann in chains], w.beta))
     chains = [ch if r.sign[c] != 0 else ([[]] * F, [[]] * F) for c, ch in enumerate(chains)]
-    base = mk(setup.seed)
+    base = mk(setup.seed + 100 * seed_offset)
     base.set_configs(chains)
-    base.sweep(therm)
+    therm, therm_order = _thermalise(base)
     # training pairs from the uniform chains
     t0 = time.perf_counter()
     Xs, Ts = [], []
@@ -277,29 +333,44 @@ def measure_ess(torch, hyb, I, therm=2000, harvests=100, train_steps=1000, moves
               [list(st["ann"][c, f, :st["k"][c, f]]) for f in range(F)]) for c in range(setup.n_chains)]
     base.close()
     out = {"workload": setup.name, "n_chains": setup.n_chains, "observable": "G(beta/2), flavor average",
-           "training": {"samples": int(X.shape[0]), "steps": train_steps, "batch": 512, "seconds": train_s}}
-    for mode, seed in (("uniform", setup.seed + 1), ("learned", setup.seed + 1)):
-        mc = mk(seed)
+           "estimator": f"blocking, {n_blocks} blocks of {moves // n_blocks} moves per chain",
+           "training": {"samples": int(X.shape[0]), "steps": train_steps, "batch": 512, "seconds": train_s},
+           "thermalisation": {"moves": therm, "mean_order": therm_order}, "eps": eps}
+    singles, runs = [], {}
+    for mode in ("uniform", "learned"):
+        mc = mk(setup.seed + 1 + 100 * seed_offset)
         mc.set_configs(start)
         if mode == "learned":
-            mc.attach_mlp(net, eps=0.1)
-        mc.sweep(1)
-        one, _ = _g_half(mc, w.beta, n_tau)           # one measurement per chain
+            mc.attach_mlp(net, eps=eps)
+        for _ in range(snapshots):                    # single measurements (one move each)
+            mc.reset_measurements()
+            mc.sweep(1)
+            g1, _, nm1 = mc.accumulators()
+            singles.append(_sg_half(g1, nm1, w.beta, n_tau))
         mc.reset_measurements()
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        mc.sweep(moves)
+        blocks, sg_tot, s_tot = _g_blocks(mc, w.beta, n_tau, n_blocks, moves)
         dt = time.perf_counter() - t1
-        means, nm = _g_half(mc, w.beta, n_tau)
-        ok = np.isfinite(one) & np.isfinite(means)
-        var1, varm = float(np.var(one[ok], ddof=1)), float(np.var(means[ok], ddof=1))
-        ess = float(ok.sum() * min(var1 / varm, float(moves))) if varm > 0 else float("nan")
         s2 = mc.stats()
+        runs[mode] = (blocks, dt, sg_tot, s_tot, s2)
+        mc.close()
+    var1 = float(np.var(np.concatenate(singles), ddof=1))
+    for mode, (blocks, dt, sg_tot, s_tot, s2) in runs.items():
+        means = blocks.mean(axis=1)
+        ok = np.all(np.isfinite(blocks), axis=1)
+        var_block = float(np.mean(np.var(blocks[ok], axis=1, ddof=1)) / n_blocks)
+        var_cross = float(np.var(means[ok], ddof=1))
+        ess_b = float(ok.sum() * min(var1 / var_block, float(moves))) if var_block > 0 else float("nan")
+        ess_c = float(ok.sum() * min(var1 / var_cross, float(moves))) if var_cross > 0 else float("nan")
+        ess = ess_c
         out[mode] = {"moves": moves, "wall_s": dt, "ess": ess, "ess_per_s": ess / dt,
+                     "ess_cross_chain": ess_c, "ess_blocking": ess_b,
                      "acceptance": (s2["insert_accepted"] + s2["remove_accepted"]) / max(1, s2["moves"]),
                      "mean_order": s2["order_sum"] / max(1, s2["moves"]), "sign_avg": s2["sign_sum"] / max(1, s2["moves"]),
-                     "g_half": float(np.mean(means[ok]))}
-        mc.close()
+                     "g_half": float(np.sum(sg_tot) / np.sum(s_tot))}
+    out["var_single"] = var1
+    out["headline_estimator"] = "across chains"
     out["learned_over_uniform_ess_per_s"] = out["learned"]["ess_per_s"] / out["uniform"]["ess_per_s"]
     net.close()
     return out
@@ -350,6 +421,9 @@ def main():
     ap.add_argument("--spmm-only", action="store_true", help="only the block SpMM bandwidth benchmark")
     ap.add_argument("--no-ess", action="store_true", help="skip the learned vs uniform ESS measurement")
     ap.add_argument("--ess-only", action="store_true", help="only the learned vs uniform ESS measurement")
+    ap.add_argument("--ess-moves", type=int, default=20000, help="measured moves per sampler")
+    ap.add_argument("--ess-seed", type=int, default=0, help="offset of the chains' seeds")
+    ap.add_argument("--ess-eps", type=float, default=0.1, help="uniform share of the learned insertion density")
     ap.add_argument("--no-seven", action="store_true", help="skip the 7-orbital mixed workload")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (3 times) and exit: the reference "
@@ -380,7 +454,7 @@ def main():
         print(json.dumps({"spmm_gated": measure_spmm(torch, hyb, I)}), flush=True)
         return
     if a.ess_only:
-        print(json.dumps({"ess": measure_ess(torch, hyb, I)}), flush=True)
+        print(json.dumps({"ess": measure_ess(torch, hyb, I, moves=a.ess_moves, eps=a.ess_eps, seed_offset=a.ess_seed)}), flush=True)
         return
     r5 = measure_workload(1, a.steps, a.warmup, torch, hyb, I, dump=a.dump)
     # Roofline of the dominant kernel (the path kernel, one launch per batch with the
@@ -427,7 +501,7 @@ def main():
     if not a.no_spmm:
         line["detail"]["spmm_gated"] = measure_spmm(torch, hyb, I)
     if not a.no_ess:
-        line["detail"]["ess"] = measure_ess(torch, hyb, I)
+        line["detail"]["ess"] = measure_ess(torch, hyb, I, moves=a.ess_moves, eps=a.ess_eps, seed_offset=a.ess_seed)
     if not a.no_cpu:
         line["cpu_baseline"] = cpu_baseline(1, a.cpu_sample)
     print(json.dumps(line), flush=True)
