@@ -5,8 +5,11 @@ BF16 at the same points as the device.  The remaining differences come from FP32
 accumulation and the rare BF16 rounding decisions it flips, so the bars are:
 - logits: 5e-3 relative in norm;
 - gradients: 2e-2 relative in norm per tensor.
-Harvested training samples are exact (integer features, bins).  A sampler using the
-learned density must sample the same distribution as the uniform one:
+Harvested training samples are exact (integer features, bins).  Learned moves replay
+the oracle's chain move by move (configurations exact, divergence allowed only where a
+BF16-level change of the logits can flip a bin draw or an acceptance, which then resyncs
+the oracle).  A sampler using the learned density must sample the same distribution as
+the uniform one:
 - G(tau) = G_sc(tau) for a free orbital;
 - learned and uniform G(tau) agree on the 2-orbital model (two-sample test).
 """
@@ -20,6 +23,7 @@ from paper_0908_0681_amd import inputs as I
 from paper_0908_0681_amd import hyb
 from oracle import mc as MC
 from oracle import mlp as NN
+from oracle import trace as T
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -232,4 +236,85 @@ def test_mc_learned_matches_uniform_two_orbital():
     # chi2/dof up to ~1.5, so the bar is 3
     print(f"learned vs uniform: max |z| {np.abs(z).max():.2f}, chi2/dof {np.mean(z ** 2):.2f}")
     assert np.abs(z).max() < 5.0 and np.mean(z ** 2) < 3.0
+    net.close()
+
+
+def _edge_distance(z, u):
+    """Distance of u * total from the nearest bin edge of the inverse-CDF draw, as a
+    fraction of the total (a draw this close to an edge can flip between bins when
+    the logits change at BF16 level)."""
+    e = np.exp(np.asarray(z, dtype=np.float64) - np.max(z))
+    c = np.cumsum(e)
+    return float(np.min(np.abs(c[:-1] - u * c[-1])) / c[-1])
+
+
+@pytest.mark.parametrize("which,n_chains,n_moves", [(6, 8, 120), (3, 3, 10)])
+def test_mc_learned_trajectory_matches_oracle(which, n_chains, n_moves):
+    """Learned moves replayed move by move: the oracle chain with the same network
+    (FP64 with BF16 rounding points) and the same counter-based uniforms against the
+    device chain (BF16 matrix cores, FP32 accumulation).  The logits differ at the
+    1e-3 level, so a move may go another way, but only where that is explained: a bin
+    draw within 1% of a bin edge, or an acceptance within 0.05 of its threshold.  The
+    oracle chain is then restarted from the device state.  Every other move must leave
+    both chains in the same configuration (times and labels exact), and at the end
+    signs, log|w| and M agree as in the uniform replay."""
+    _require_gpu()
+    setup = I.mc_setup(which, n_chains)
+    w = setup.workload
+    F = 2 * w.params.n_orb
+    kmax = setup.kmax_flavor
+    o = T.build(w.params, w.retain_window)
+    m = hyb.model_for_workload(w)
+    net = hyb.MLP(seed=17)
+    Ws, bs = _random_weights(21, scale=0.15)
+    net.set_weights(Ws, bs)
+    onet = NN.Network(Ws, bs, quantize=True)
+    eps = 0.2
+    mc = hyb.MC(m, setup.n_chains, w.beta, setup.delta, kmax=kmax, nmax_ops=512, seed=setup.seed, n_tau=10)
+    chains = []
+    for cre, ann in I.mc_initial_configs(setup):
+        try:
+            ch = MC.Chain(o, setup.delta, w.beta, cre, ann, kmax, net=onet, eps=eps)
+        except ValueError:
+            ch = MC.Chain(o, setup.delta, w.beta, [[]] * F, [[]] * F, kmax, net=onet, eps=eps)
+        chains.append(ch)
+    mc.set_configs([(ch.cre, ch.ann) for ch in chains])
+    mc.attach_mlp(net, eps=eps)
+    same = diverged = accepted = 0
+    for step in range(n_moves):
+        mc.sweep(1)
+        st = mc.state()
+        for c, ch in enumerate(chains):
+            u = MC.move_uniforms(setup.seed, c, step, calls=(0, 1, 2, 3, 4))
+            f = min(int(u[0] * F), F - 1)
+            near_edge = False
+            if u[1] < 0.5 and len(ch.cre[f]) < kmax and not u[8] < eps:
+                z = onet.forward(NN.features(ch.cre, ch.ann, f, w.beta)[None])["Z3"][0]
+                near_edge = min(_edge_distance(z[:NN.BINS], u[2]), _edge_distance(z[NN.BINS:], u[3])) < 0.01
+            ch.last_margin = np.inf
+            kind, a = ch.step(u)
+            accepted += a
+            dev = ([list(st["cre"][c, g, :st["k"][c, g]]) for g in range(F)],
+                   [list(st["ann"][c, g, :st["k"][c, g]]) for g in range(F)])
+            if dev == (ch.cre, ch.ann):
+                same += 1
+                continue
+            assert near_edge or ch.last_margin < 0.05, (which, step, c, kind, ch.last_margin)
+            diverged += 1
+            chains[c] = MC.Chain(o, setup.delta, w.beta, dev[0], dev[1], kmax, net=onet, eps=eps)
+    print(f"learned replay: {same} moves identical, {diverged} explained divergences, {accepted} accepted")
+    assert diverged <= max(2, 0.05 * (same + diverged))
+    st = mc.state(with_M=True)
+    worst_M = worst_w = 0.0
+    for c, ch in enumerate(chains):
+        for g in range(F):
+            k = len(ch.cre[g])
+            assert st["k"][c, g] == k
+            if k:
+                Mi = np.linalg.inv(MC.hyb_matrix(setup.delta, w.beta, ch.cre[g], ch.ann[g]))
+                worst_M = max(worst_M, np.max(np.abs(st["M"][c, g, :k, :k] - Mi)) / np.max(np.abs(Mi)))
+        assert st["sign"][c] == ch.sign, c
+        worst_w = max(worst_w, abs(st["logw"][c] - ch.logw))
+    assert worst_M <= 1e-10 and worst_w <= 1e-10, (worst_M, worst_w)
+    mc.close()
     net.close()
