@@ -474,8 +474,8 @@ struct PathEngine {
   // Q[m-2][i] in the last row and column.  Its eigenvalues are the roots of
   //   h(lam) = alpha_{m-1} - lam - sum_i z_i^2 / (theta_i - lam),
   // which decreases between poles: one root below theta_0, one between each pair of
-  // neighbouring poles, one above theta_{n-1}.  Lane k finds root k as an offset x
-  // from its nearer pole (so that roots close to a pole keep their relative
+  // neighbouring poles, one above theta_{n-1}.  A group of lanes finds root k as an
+  // offset x from its nearer pole (so that roots close to a pole keep their relative
   // accuracy) by steps on a rational model of h, bracketed by bisection.  The
   // couplings are then recomputed from the computed roots with Loewner's formula,
   // which makes the roots exact for a nearby arrowhead and the eigenvectors
@@ -505,37 +505,51 @@ struct PathEngine {
     if (wave_any(bad)) return false;
     wave_sync();
 
+    // Lanes in groups of G (8 when m <= 8, else 4): group g finds root g.  A lane
+    // takes the poles i = sub, sub + G, ... of the pole sums, and the group adds its
+    // lanes' parts with DPP, so every lane of the group holds the same sums (additions
+    // are commutative, the butterfly order is the same on every lane) and the group's
+    // iteration is uniform.
+    const int G = (m <= 8) ? 8 : 4;
+    const int k = lane / G, sub = lane - (lane / G) * G;
+    const bool act = k < m;
+    auto gsum = [&](double v) {
+      v += dpp_d<0xB1>(v);                 // lane ^ 1
+      v += dpp_d<0x4E>(v);                 // lane ^ 2
+      if (G == 8) v += dpp_d<0x141>(v);    // the other quad of the half-row
+      return v;
+    };
     // h and the parts of -h' from poles left (dl_sum) and right (dr_sum) of root k,
     // at lam = tho + x; sabs = sum of |z_i^2 / (theta_i - lam)|
-    auto eval = [&](int k, double tho, double x, double& dl_sum, double& dr_sum, double& sabs) {
-      double sum = 0.0;
-      dl_sum = 0.0;
-      dr_sum = 0.0;
-      sabs = 0.0;
-#pragma unroll 2
-      for (int i = 0; i < n; ++i) {
+    auto eval = [&](double tho, double x, double& dl_sum, double& dr_sum, double& sabs) {
+      double sum = 0.0, dl = 0.0, dr = 0.0, sa = 0.0;
+      for (int i = sub; i < n; i += G) {
         const double r = rcp_d((W.tz[2 * i] - tho) - x);
         const double ti = W.tz[2 * i + 1] * r;
         sum += ti;
-        if (i < k) dl_sum += ti * r;
-        else dr_sum += ti * r;
-        sabs += fabs(ti);
+        if (i < k) dl += ti * r;
+        else dr += ti * r;
+        sa += fabs(ti);
       }
+      sum = gsum(sum);
+      dl_sum = gsum(dl);
+      dr_sum = gsum(dr);
+      sabs = gsum(sa);
       return (alpha - tho) - x - sum;
     };
 
-    double tho = 0.0, x = 0.0;
-    bool conv = true;
-    if (lane < m) {
-      const int k = lane;
-      double lo, hi, h, dls, drs, sabs;
-      double DL = 0.0, DR = 0.0;  // poles bracketing an interior root, relative to tho
-      const bool interior = (k > 0 && k < n);
-      const double tl = (k > 0) ? th[k - 1] : 0.0, tr = (k < n) ? th[k] : 0.0;
-      int o;  // origin pole
+    double tho = 0.0, x = 0.0, lo = 0.0, hi = 0.0, h = 0.0, dls = 0.0, drs = 0.0, sabs = 0.0;
+    double DL = 0.0, DR = 0.0;  // poles bracketing an interior root, relative to tho
+    const bool interior = act && k > 0 && k < n;
+    const double tl = (act && k > 0) ? th[k - 1] : 0.0, tr = (act && k < n) ? th[k] : 0.0;
+    int o = 0;  // origin pole
+    {
+      // interior roots: the midpoint decides the nearer pole (evaluated by every group
+      // so that the DPP sums stay uniform; outer groups discard it)
+      const double g = tr - tl;
+      const double hm = eval(tl, 0.5 * g, dls, drs, sabs);
       if (interior) {
-        const double g = tr - tl;
-        h = eval(k, tl, 0.5 * g, dls, drs, sabs);
+        h = hm;
         if (h > 0.0) {  // root in the right half: origin at theta_k
           o = k;
           tho = tr;
@@ -551,76 +565,107 @@ struct PathEngine {
           hi = x;
           DR = g;
         }
-      } else {
+      } else if (act) {
         o = (k == 0) ? 0 : n - 1;
         tho = (k == 0) ? tr : tl;
+      }
+    }
+    // the outer roots' Weyl bounds and every group's start: the root of the model that
+    // keeps the linear term and the origin pole and freezes the other poles at
+    // lam = theta_o
+    {
+      double a = 0.0, zp = 0.0;
+      for (int i = sub; i < n; i += G) {
+        zp += W.tz[2 * i + 1];
+        if (i != o) a += W.tz[2 * i + 1] * rcp_d(W.tz[2 * i] - tho);
+      }
+      a = gsum(a);
+      const double zn = sqrt(gsum(zp));
+      if (act && !interior) {
         const double A0 = alpha - tho;
-        double zn2 = 0.0;
-        for (int i = 0; i < n; ++i) zn2 += W.tz[2 * i + 1];
-        const double zn = sqrt(zn2);
-        lo = (k == 0) ? 2.0 * (fmin(0.0, A0) - zn) : 0.0;  // Weyl bounds
+        lo = (k == 0) ? 2.0 * (fmin(0.0, A0) - zn) : 0.0;
         hi = (k == 0) ? 0.0 : 2.0 * (fmax(0.0, A0) + zn);
       }
-      // start from the root of the model that keeps the linear term and the origin
-      // pole and freezes the other poles at lam = theta_o
-      {
-        double a = 0.0;
-#pragma unroll 2
-        for (int i = 0; i < n; ++i)
-          if (i != o) a += W.tz[2 * i + 1] * rcp_d(W.tz[2 * i] - tho);
-        const double xp = pole_root((alpha - tho) - a, W.tz[2 * o + 1], k > o);
-        if (xp > lo && xp < hi) x = xp;
-        else if (!interior) x = 0.5 * (lo + hi);
-        if (x == xp || !interior) h = eval(k, tho, x, dls, drs, sabs);
-      }
-      conv = false;
-      for (int it = 0; it < 60; ++it) {
-        if (!(h == h)) break;
-        if (h > 0.0) lo = x;
-        else hi = x;
-        const double A0 = alpha - tho, hp = 1.0 + dls + drs;
-        const double errb = eps * (8.0 * sabs + 4.0 * fabs(A0) + 4.0 * fabs(x) + 2.0 * fabs(x) * hp);
-        if (fabs(h) <= errb || hi - lo <= 4.0 * eps * fmax(fabs(lo), fabs(hi))) {
-          conv = true;
-          break;
+      const double xp = act ? pole_root((alpha - tho) - a, W.tz[2 * o + 1], k > o) : 0.0;
+      bool take = false;
+      if (act) {
+        if (xp > lo && xp < hi) {
+          x = xp;
+          take = true;
+        } else if (!interior) {
+          x = 0.5 * (lo + hi);
+          take = true;
         }
-        // one-pole model: the exact linear term and the origin pole carrying all of
-        // the poles' part of -h' (the whole step for an outer root)
-        const double s1 = (dls + drs) * x * x;
-        const double a1 = ((alpha - tho) - x - h) + (dls + drs) * x;
-        double xn = pole_root(A0 - a1, s1, x > 0.0);
-        if (interior) {
-          // two-pole model: the linear term, and the bracketing poles carrying the
-          // poles' part of -h' of their side; a few Newton steps from the one-pole root
-          const double dl = DL - x, dr = DR - x;
-          const double sL = dls * dl * dl, sR = drs * dr * dr;
-          const double c = h + x + dls * dl + drs * dr;
-          double y = (xn > lo && xn < hi) ? xn : x;
-          for (int q = 0; q < 3; ++q) {
-            const double rl = rcp_d(DL - y), rr = rcp_d(DR - y);
-            const double f = c - y - sL * rl - sR * rr;
-            const double fp = -1.0 - sL * rl * rl - sR * rr * rr;
-            const double y2 = y - f * rcp_d(fp);
-            if (!(y2 > lo && y2 < hi)) break;
-            y = y2;
+      }
+      double d1, d2, d3;
+      const double he = eval(tho, x, d1, d2, d3);
+      if (take) {
+        h = he;
+        dls = d1;
+        drs = d2;
+        sabs = d3;
+      }
+    }
+    bool done = !act, conv = !act;
+    for (int it = 0; it < 60; ++it) {
+      if (!done) {
+        if (!(h == h)) {
+          done = true;
+        } else {
+          if (h > 0.0) lo = x;
+          else hi = x;
+          const double A0 = alpha - tho, hp = 1.0 + dls + drs;
+          const double errb = eps * (8.0 * sabs + 4.0 * fabs(A0) + 4.0 * fabs(x) + 2.0 * fabs(x) * hp);
+          if (fabs(h) <= errb || hi - lo <= 4.0 * eps * fmax(fabs(lo), fabs(hi))) {
+            done = conv = true;
+          } else {
+            // one-pole model: the exact linear term and the origin pole carrying all
+            // of the poles' part of -h' (the whole step for an outer root)
+            const double s1 = (dls + drs) * x * x;
+            const double a1 = ((alpha - tho) - x - h) + (dls + drs) * x;
+            double xn = pole_root(A0 - a1, s1, x > 0.0);
+            if (interior) {
+              // two-pole model: the linear term, and the bracketing poles carrying the
+              // poles' part of -h' of their side; a few Newton steps from the one-pole root
+              const double dl = DL - x, dr = DR - x;
+              const double sL = dls * dl * dl, sR = drs * dr * dr;
+              const double c = h + x + dls * dl + drs * dr;
+              double y = (xn > lo && xn < hi) ? xn : x;
+              for (int q = 0; q < 3; ++q) {
+                const double rl = rcp_d(DL - y), rr = rcp_d(DR - y);
+                const double f = c - y - sL * rl - sR * rr;
+                const double fp = -1.0 - sL * rl * rl - sR * rr * rr;
+                const double y2 = y - f * rcp_d(fp);
+                if (!(y2 > lo && y2 < hi)) break;
+                y = y2;
+              }
+              xn = y;
+            }
+            const bool bis = !(xn > lo && xn < hi);
+            if (bis) xn = 0.5 * (lo + hi);
+            if (xn == x) {
+              done = conv = true;
+            } else if (!bis && fabs(xn - x) <= 0x1p-30 * fabs(xn)) {
+              // a model step this small leaves an error far below rounding: take it
+              x = xn;
+              done = conv = true;
+            } else {
+              x = xn;
+            }
           }
-          xn = y;
         }
-        const bool bis = !(xn > lo && xn < hi);
-        if (bis) xn = 0.5 * (lo + hi);
-        if (xn == x) {
-          conv = true;
-          break;
-        }
-        // a model step this small leaves an error far below rounding: take it
-        if (!bis && fabs(xn - x) <= 0x1p-30 * fabs(xn)) {
-          x = xn;
-          conv = true;
-          break;
-        }
-        x = xn;
-        h = eval(k, tho, x, dls, drs, sabs);
       }
+      if (!wave_any(!done)) break;
+      double d1, d2, d3;
+      const double he = eval(tho, x, d1, d2, d3);
+      if (!done) {
+        h = he;
+        dls = d1;
+        drs = d2;
+        sabs = d3;
+      }
+    }
+    if (act && sub == 0) {
       W.tho[k] = tho;
       W.xr[k] = x;
       W.a[cur ^ 1][k] = tho + x;
@@ -664,7 +709,7 @@ struct PathEngine {
 #pragma unroll
       for (int i = 0; i < NP; ++i) {
         if (i < n) {
-          const double ui = W.zh[i] * rcp_d((tho - W.tz[2 * i]) + x);
+          const double ui = W.zh[i] * rcp_d((W.tho[lane] - W.tz[2 * i]) + W.xr[lane]);
           W.u[i * QLD + lane] = ui;
           nrm += ui * ui;
         }
