@@ -376,6 +376,27 @@ def measure_ess(torch, hyb, I, harvests=100, train_steps=1000, moves=20000, n_ta
     return out
 
 
+def oracle_feasible_paths(k):
+    """Feasible (configuration, retained state) paths of workload k by the oracle's own
+    sector walk (block transitions only, no arithmetic)."""
+    from paper_0908_0681_amd import inputs as I
+    from oracle import trace as T
+    w = I.workload(k)
+    o = T.build(w.params, w.retain_window)
+    b = w.batch()
+    n = 0
+    for c in range(b.n_configs):
+        tau, fl, dg = b.config(c)
+        for r in range(len(o.R.block)):
+            b0 = blk = int(o.R.block[r])
+            for q in range(len(tau)):
+                blk = o.target_block(blk, int(fl[q]), int(dg[q]))
+                if blk < 0:
+                    break
+            n += int(blk == b0)
+    return n
+
+
 def cpu_baseline(k, n_sample):
     """The FP64 oracle as it stands, on the first n_sample configurations."""
     import numpy as np
@@ -504,6 +525,9 @@ def main():
         line["detail"]["ess"] = measure_ess(torch, hyb, I, moves=a.ess_moves, eps=a.ess_eps, seed_offset=a.ess_seed)
     if not a.no_cpu:
         line["cpu_baseline"] = cpu_baseline(1, a.cpu_sample)
+        ofp = oracle_feasible_paths(1)
+        line["detail"]["oracle_feasible_paths"] = ofp
+        line["detail"]["feasible_paths_match"] = ofp == line["detail"]["feasible_paths"]
     print(json.dumps(line), flush=True)
 
 
