@@ -626,12 +626,12 @@ struct PathEngine {
             double xn = pole_root(A0 - a1, s1, x > 0.0);
             if (interior) {
               // two-pole model: the linear term, and the bracketing poles carrying the
-              // poles' part of -h' of their side; a few Newton steps from the one-pole root
+              // poles' part of -h' of their side; two Newton steps from the one-pole root
               const double dl = DL - x, dr = DR - x;
               const double sL = dls * dl * dl, sR = drs * dr * dr;
               const double c = h + x + dls * dl + drs * dr;
               double y = (xn > lo && xn < hi) ? xn : x;
-              for (int q = 0; q < 3; ++q) {
+              for (int q = 0; q < 2; ++q) {
                 const double rl = rcp_d(DL - y), rr = rcp_d(DR - y);
                 const double f = c - y - sL * rl - sR * rr;
                 const double fp = -1.0 - sL * rl * rl - sR * rr * rr;
