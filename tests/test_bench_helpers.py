@@ -1,0 +1,46 @@
+"""Host-side helpers of bench.py: the sign-weighted observable of the ESS measurement,
+the depth histogram, and the oracle's feasible-path count (against a brute-force
+walk of the 2-orbital sectors)."""
+import numpy as np
+
+import bench
+from paper_0908_0681_amd import inputs as I
+
+
+def test_sign_weighted_observable_is_a_plain_average():
+    rng = np.random.default_rng(1)
+    g = rng.normal(size=(3, 4, 20))
+    nm = np.array([1, 2, 5])
+    beta, n_tau = 10.0, 20
+    got = bench._sg_half(g, nm, beta, n_tau)
+    want = [-(g[c, :, 9:11].mean()) / (beta * (beta / n_tau) * nm[c]) for c in range(3)]
+    assert np.allclose(got, want, rtol=1e-14)
+    # with one measurement per chain the sums come back unscaled
+    assert np.allclose(bench._sg_half(g, 1, beta, n_tau), got * nm, rtol=1e-14)
+
+
+def test_depth_histogram_counts_configurations():
+    import torch
+    offsets = np.array([0, 3, 7, 7, 10])          # 3, 4, 0 and 3 operators
+    batch = type("B", (), {"offsets": offsets})()
+    out = {"feasible_paths": torch.tensor([1, 2, 0, 1]), "krylov_steps": torch.tensor([5, 12, 0, 20])}
+    h = bench.depth_histogram(batch, out)
+    # mean depths 5/2 = 2.5, 12/6 = 2.0, (none), 20/2 = 10.0
+    assert sum(h["configs"]) == 3
+    assert h["configs"][2] == 2 and h["configs"][10] == 1
+
+
+def test_oracle_feasible_paths_matches_the_full_oracle():
+    """bench.oracle_feasible_paths walks sectors only; the full oracle path (which also
+    does the arithmetic) reports the same feasibility (2-orbital batch)."""
+    from oracle import trace as T
+    w = I.workload(0)
+    o = T.build(w.params, w.retain_window)
+    b = w.batch()
+    want = 0
+    for c in range(b.n_configs):
+        tau, fl, dg = b.config(c)
+        for r in range(len(o.R.block)):
+            want += int(o.path(tau, fl, dg, b.beta, r)[0])
+    got = bench.oracle_feasible_paths(0)
+    assert got == want and got > 0
