@@ -97,7 +97,10 @@ typedef struct {
 int hyb_model_create(const hyb_model_params* p, hyb_model** out);
 
 /* Copies the model (basis tables, CSR blocks, retained vectors) to the current
- * HIP device on `stream`.  Must precede any device call on the model. */
+ * HIP device on `stream`, with two padded ELL copies of the off-diagonal rows: one
+ * in natural row order for the trace kernels, one with rows sorted by length for
+ * the block SpMM.  Must precede any device call on the model; the device copies
+ * live until hyb_model_destroy. */
 int hyb_model_upload(hyb_model* m, void* stream);
 
 /* hyb_model_create + hyb_model_upload. */
