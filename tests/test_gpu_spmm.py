@@ -58,6 +58,40 @@ def test_block_spmm_matches_oracle(k, n_up, n_dn, n_vec):
     assert err <= 2e-6
 
 
+def test_block_spmm_full_size_sampled():
+    """The benchmark's pass: the 7-orbital (3,4) block on N_v = 262144 vectors.  Three
+    panels (first, a seeded middle one, last) are checked against the oracle's block,
+    and every panel through linearity: the sum of all output panels against the block
+    applied to the sum of all input panels (both sums in FP64)."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    w = I.workload(2)
+    m = hyb.model_for_workload(w)
+    b = Fk.block_key(w.params.n_orb, 3, 4)
+    A = _oracle_block(w.params, 3, 4)
+    d, n_vec = A.shape[0], 262144
+    gen = torch.Generator(device="cuda").manual_seed(2024)
+    Xd = torch.randn(n_vec // 16, d, 16, device="cuda", dtype=torch.float32, generator=gen)
+    Yd = torch.full_like(Xd, float("nan"))
+    m.block_spmm(b, Xd, Yd, n_vec)
+    torch.cuda.synchronize()
+    assert bool(torch.isfinite(Yd).all())
+    mid = int(np.random.default_rng(5).integers(1, n_vec // 16 - 1))
+    for p in (0, mid, n_vec // 16 - 1):
+        X = Xd[p].double().cpu().numpy()
+        Y = Yd[p].cpu().numpy()
+        ref = A @ X
+        err = np.linalg.norm(Y - ref) / np.linalg.norm(ref)
+        print(f"panel {p}: relative error {err:.2e}")
+        assert err <= 2e-6, p
+    xs = Xd.sum(dim=0, dtype=torch.float64).cpu().numpy()
+    ys = Yd.sum(dim=0, dtype=torch.float64).cpu().numpy()
+    ref = A @ xs
+    err = np.linalg.norm(ys - ref) / np.linalg.norm(ref)
+    print(f"sum of all {n_vec // 16} panels: relative error {err:.2e}")
+    assert err <= 2e-6
+
+
 def test_block_spmm_rejects_bad_sizes():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")

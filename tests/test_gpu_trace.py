@@ -271,6 +271,21 @@ def test_full_size_five_orbital_sampled(w1):
     assert np.all(r.feasible_paths >= 1)
 
 
+def test_full_size_seven_orbital_sampled(w2):
+    """The full 1024-configuration 7-orbital batch in the benchmark's launch
+    configuration (mixed precision); a seeded sample is checked against the oracle."""
+    w, m, o = w2
+    b = w.batch()
+    r = m.trace_batch(b)
+    rng = np.random.default_rng(19)
+    idx = np.sort(rng.choice(b.n_configs, 8, replace=False))
+    sub = hyb.TraceResult(r.sign[idx], r.log_abs[idx], r.krylov_steps[idx], r.substeps[idx],
+                          r.feasible_paths[idx])
+    worst = compare(sub, o.trace_batch(b, configs=idx), 1e-5, o, b.subset(idx), unit=U32)
+    print(f"worst relative error, sampled full 7-orbital batch: {worst:.3e}")
+    assert np.all(r.feasible_paths >= 1) and np.all(np.isin(r.sign, (-1, 0, 1)))
+
+
 @pytest.mark.parametrize("k", [1, 2])
 def test_chunked_schedule_identical(k):
     """One launch per step, per chunk of operators, or per whole path: the same
