@@ -145,31 +145,35 @@ def sum_intervals(batch, out, torch):
     return int(np.sum(feas * np.maximum(nops - 1, 0)))
 
 
-def measure_mc(torch, hyb, I, moves=40, warm=10):
-    """Chain-moves per second of the Monte Carlo layer on the 5-orbital model with
-    a semicircular bath: 256 chains started at total pair numbers uniform in
-    0..200, one pair insertion or removal per chain and move, each with a Krylov
-    trace of the proposed configuration and O(k^2) determinant updates."""
-    setup = I.mc_setup(3)
+def measure_mc(torch, hyb, I, moves=40, warm=10, which=3, n_chains=None, graphs=False, moves_per_sweep=1):
+    """Chain-moves per second of the Monte Carlo layer.  which = 3: the 5-orbital
+    model with a semicircular bath, 256 chains started at total pair numbers uniform
+    in 0..200; which = 6: the 2-orbital model (short traces, so launch overhead
+    counts).  One pair insertion or removal per chain and move, each with a Krylov
+    trace of the proposed configuration and O(k^2) determinant updates.  graphs:
+    every sweep of moves_per_sweep moves is replayed from a captured HIP graph."""
+    setup = I.mc_setup(which, n_chains)
     w = setup.workload
     m = hyb.model_for_workload(w)
     mc = hyb.MC(m, setup.n_chains, w.beta, setup.delta, kmax=setup.kmax_flavor, nmax_ops=512,
-                seed=setup.seed, n_tau=200, meas_every=10)
+                seed=setup.seed, n_tau=200, meas_every=10, moves_per_sweep=moves_per_sweep)
+    mc.set_graphs(graphs)
     chains = I.mc_initial_configs(setup)
     # a start whose trace vanishes is replaced by the empty configuration
     r = m.trace_batch(I.from_lists([I.mc_merged(cre, ann) for cre, ann in chains], w.beta))
     F = 2 * w.params.n_orb
     chains = [ch if r.sign[c] != 0 else ([[]] * F, [[]] * F) for c, ch in enumerate(chains)]
     mc.set_configs(chains)
-    mc.sweep(warm)
+    mc.sweep(warm // moves_per_sweep)
     mc.reset_measurements()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    mc.sweep(moves)
+    mc.sweep(moves // moves_per_sweep)
     dt = time.perf_counter() - t0
     st = mc.stats()
     acc = (st["insert_accepted"] + st["remove_accepted"]) / max(1, st["moves"])
-    res = {"workload": setup.name, "n_chains": setup.n_chains, "moves": moves,
+    res = {"workload": setup.name, "n_chains": setup.n_chains, "moves": moves, "graphs": graphs,
+           "moves_per_sweep": moves_per_sweep,
            "chain_moves_per_s": setup.n_chains * moves / dt, "ms_per_move": dt / moves * 1e3,
            "acceptance": acc, "mean_order": st["order_sum"] / max(1, st["moves"]),
            "sign_avg": st["sign_sum"] / max(1, st["moves"])}
@@ -519,6 +523,11 @@ def main():
             "substeps", "feasible_paths", "host_buffers")}
     if not a.no_mc:
         line["detail"]["mc"] = measure_mc(torch, hyb, I)
+        line["detail"]["mc"]["graph_replay"] = measure_mc(torch, hyb, I, graphs=True, moves_per_sweep=10)
+        line["detail"]["mc_2orb"] = {
+            "direct": measure_mc(torch, hyb, I, moves=2000, warm=200, which=6, n_chains=256),
+            "graph_replay": measure_mc(torch, hyb, I, moves=2000, warm=200, which=6, n_chains=256, graphs=True,
+                                       moves_per_sweep=100)}
     if not a.no_spmm:
         line["detail"]["spmm_gated"] = measure_spmm(torch, hyb, I)
     if not a.no_ess:

@@ -302,6 +302,15 @@ int hyb_mc_get_accumulators(const hyb_mc* mc, double* gacc, double* meas_sign, i
 int hyb_mc_measure(const hyb_mc* mc, double* G, double* sign_avg, void* stream);
 int hyb_mc_reset_measurements(hyb_mc* mc, void* stream);
 int hyb_mc_step_count(const hyb_mc* mc, int64_t* step);
+/* enable != 0: hyb_mc_sweep captures one sweep (moves_per_sweep moves of every chain,
+ * with no host synchronisation inside) into a HIP graph on first use and replays it
+ * n_sweeps times on `stream`.  The move counter lives on the device, so every replay
+ * draws new random numbers, and the chains evolve bit for bit as with enable = 0.  The
+ * sweep is captured again when anything it depends on has changed: the attached network
+ * or its buffers, the mixture weight, the model's device copy or its kernel variant.
+ * enable = 0 (the default) launches every move directly and frees the graph.  Capture
+ * uses a private stream of the default priority; calls on one hyb_mc must not overlap. */
+int hyb_mc_set_graphs(hyb_mc* mc, int32_t enable);
 
 /* ---- learned insertion proposal ---------------------------------------------- */
 

@@ -85,6 +85,7 @@ struct hyb_model {
   std::vector<int64_t> ell_off;
   // device side
   bool uploaded = false;
+  uint64_t dev_gen = 0;     // bumped by every upload: device pointers captured earlier are stale
   hyb::DeviceModel dev;
   int variant = -1;         // trace kernel variant (-1 = automatic)
   int chunk = 1;            // operators per path-step launch (1 = one launch per step kind)

@@ -37,17 +37,27 @@ namespace hyb {
 #include "mc_kernels.h"
 namespace hyb {
 
-__global__ __launch_bounds__(64) void k_mc_propose(MCParams Q, int64_t step) {
+// The move counter lives on the device: move `off` of a launch sequence is move
+// *Q.step_dev + off, and k_mc_advance moves the counter on at the end of the
+// sequence.  A captured sweep therefore draws new random numbers on every replay.
+__global__ __launch_bounds__(64) void k_mc_propose(MCParams Q, int64_t off) {
   __shared__ double sb[64], sc[64];
-  mc_propose(Q, blockIdx.x, step, sb, sc);
+  mc_propose(Q, blockIdx.x, *Q.step_dev + off, sb, sc);
 }
 
-__global__ __launch_bounds__(64) void k_mc_accept(MCParams Q, int64_t step, int measure) {
+__global__ __launch_bounds__(64) void k_mc_accept(MCParams Q, int64_t off, int32_t meas_every) {
   extern __shared__ double canon[];
-  mc_accept(Q, blockIdx.x, step, measure, canon);
+  const int64_t step = *Q.step_dev + off;
+  mc_accept(Q, blockIdx.x, step, ((step + 1) % meas_every) == 0 ? 1 : 0, canon);
 }
 
-__global__ __launch_bounds__(64) void k_mc_choose(MCParams Q, int64_t step) { mc_choose(Q, blockIdx.x, step); }
+__global__ __launch_bounds__(64) void k_mc_choose(MCParams Q, int64_t off) {
+  mc_choose(Q, blockIdx.x, *Q.step_dev + off);
+}
+
+__global__ void k_mc_set_step(int64_t* step, int64_t value, int64_t add) {
+  if (threadIdx.x == 0) step[0] = (add ? step[0] : 0) + value;
+}
 
 __global__ __launch_bounds__(64) void k_mc_harvest(MCParams Q, int64_t index, __bf16* X, int32_t* T) {
   mc_harvest(Q, blockIdx.x, index, X, T);
@@ -73,6 +83,12 @@ struct hyb_mc {
   __bf16* X = nullptr;         // [C][MLP_IN] features of the proposing configurations
   float* logits = nullptr;     // [C][MLP_OUT]
   std::vector<void*> allocs;
+  // sweeps replayed from a captured HIP graph (hyb_mc_set_graphs)
+  bool graphs = false;
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  std::vector<unsigned char> gkey;  // everything the captured launches depend on
 };
 
 namespace {
@@ -149,12 +165,90 @@ int run_traces(hyb_mc* mc, hipStream_t s) {
                         mc->p.nmax_ops, mc->p.beta, mc->trace_ws, mc->t_log, mc->t_sign, mc->err, s);
 }
 
+// Enqueues `moves` moves of every chain and the advance of the device move counter
+// on s.  Nothing here synchronises with the host, so the sequence can be captured.
+int launch_moves(hyb_mc* mc, int64_t moves, hipStream_t s) {
+  const int C = mc->p.n_chains;
+  const size_t smem = sizeof(double) * std::max(mc->p.nmax_ops, 64);
+  for (int64_t mv = 0; mv < moves; ++mv) {
+    if (mc->mlp) {
+      k_mc_choose<<<C, 64, 0, s>>>(mc->Q, mv);
+      MlpActs a = mc->mlp->acts;
+      a.z3 = mc->logits;
+      int rc0 = mlp_forward(mc->mlp, C, mc->X, a, s);
+      if (rc0) return rc0;
+    }
+    k_mc_propose<<<C, 64, 0, s>>>(mc->Q, mv);
+    int rc = run_traces(mc, s);
+    if (rc) return rc;
+    k_mc_accept<<<C, 64, smem, s>>>(mc->Q, mv, mc->p.meas_every);
+    MC_HIP_TRY(hipGetLastError());
+  }
+  k_mc_set_step<<<1, 64, 0, s>>>(mc->Q.step_dev, moves, 1);
+  MC_HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+// What a captured sweep depends on: the chain parameters (device pointers, learned
+// flag, mixture weight), the sweep length, the network's buffers, the model's
+// device copy and its kernel variant.  A change of any of them forces a new capture.
+std::vector<unsigned char> sweep_key(const hyb_mc* mc) {
+  std::vector<unsigned char> k;
+  auto put = [&k](const void* p, size_t n) {
+    const unsigned char* b = static_cast<const unsigned char*>(p);
+    k.insert(k.end(), b, b + n);
+  };
+  put(&mc->Q, sizeof(mc->Q));
+  put(&mc->p.moves_per_sweep, sizeof(mc->p.moves_per_sweep));
+  put(&mc->p.meas_every, sizeof(mc->p.meas_every));
+  put(&mc->mlp, sizeof(mc->mlp));
+  if (mc->mlp) {
+    put(&mc->mlp->acts, sizeof(mc->mlp->acts));
+    put(mc->mlp->wb, sizeof(mc->mlp->wb));
+    put(mc->mlp->bias, sizeof(mc->mlp->bias));
+  }
+  put(&mc->m->dev_gen, sizeof(mc->m->dev_gen));
+  const int v = trace_resident_variant(mc->m);
+  put(&v, sizeof(v));
+  return k;
+}
+
+void drop_graph(hyb_mc* mc) {
+  if (mc->gexec) (void)hipGraphExecDestroy(mc->gexec);
+  if (mc->graph) (void)hipGraphDestroy(mc->graph);
+  mc->gexec = nullptr;
+  mc->graph = nullptr;
+  mc->gkey.clear();
+}
+
+// Captures one sweep (moves_per_sweep moves and the counter advance) on a private
+// stream and instantiates it.
+int capture_sweep(hyb_mc* mc) {
+  drop_graph(mc);
+  if (!mc->cap_stream) MC_HIP_TRY(hipStreamCreateWithFlags(&mc->cap_stream, hipStreamNonBlocking));
+  MC_HIP_TRY(hipStreamBeginCapture(mc->cap_stream, hipStreamCaptureModeThreadLocal));
+  const int rc = launch_moves(mc, mc->p.moves_per_sweep, mc->cap_stream);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(mc->cap_stream, &g);
+  if (rc) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess || !g) return set_error(HYB_E_HIP, "capture of a sweep failed: %s", hipGetErrorString(e));
+  mc->graph = g;
+  MC_HIP_TRY(hipGraphInstantiate(&mc->gexec, g, nullptr, nullptr, 0));
+  mc->gkey = sweep_key(mc);
+  return 0;
+}
+
 }  // namespace
 
 extern "C" {
 
 int hyb_mc_destroy(hyb_mc* mc) {
   if (!mc) return HYB_OK;
+  drop_graph(mc);
+  if (mc->cap_stream) (void)hipStreamDestroy(mc->cap_stream);
   for (void* p : mc->allocs) (void)hipFree(p);
   delete[] mc->p.delta;
   delete mc;
@@ -213,7 +307,7 @@ int hyb_mc_create(hyb_model* m, const hyb_mc_params* p, hyb_mc** out) {
       (rc = mc_alloc(mc, mc->t_log, C)) || (rc = mc_alloc(mc, mc->t_sign, C)) ||
       (rc = mc_alloc(mc, Q.stats, size_t(C) * ST_N)) || (rc = mc_alloc(mc, Q.sign_sum, C)) ||
       (rc = mc_alloc(mc, Q.gacc, size_t(C) * F * p->n_tau)) || (rc = mc_alloc(mc, Q.meas_sign, C)) ||
-      (rc = mc_alloc(mc, Q.n_meas, C)) || (rc = mc_alloc(mc, mc->err, 1)))
+      (rc = mc_alloc(mc, Q.n_meas, C)) || (rc = mc_alloc(mc, mc->err, 1)) || (rc = mc_alloc(mc, Q.step_dev, 1)))
     return fail(rc);
   char* ws = nullptr;
   if ((rc = mc_alloc(mc, ws, trace_ws_bytes(m, C)))) return fail(rc);
@@ -347,6 +441,8 @@ int hyb_mc_set_configs(hyb_mc* mc, const int32_t* k, const double* cre, const do
   MC_HIP_TRY(hipMemcpyAsync(Q.cur_logtr, tl.data(), sizeof(double) * C, hipMemcpyHostToDevice, s));
   MC_HIP_TRY(hipMemcpyAsync(Q.cur_signtr, signtr.data(), sizeof(int32_t) * C, hipMemcpyHostToDevice, s));
   MC_HIP_TRY(hipMemcpyAsync(Q.cur_sign, sign.data(), sizeof(int32_t) * C, hipMemcpyHostToDevice, s));
+  k_mc_set_step<<<1, 64, 0, s>>>(Q.step_dev, 0, 0);
+  MC_HIP_TRY(hipGetLastError());
   MC_HIP_TRY(hipStreamSynchronize(s));
   mc->step = 0;
   return HYB_OK;
@@ -356,25 +452,19 @@ int hyb_mc_sweep(hyb_mc* mc, int32_t n_sweeps, void* stream) {
   if (!mc) return set_error(HYB_E_ARG, "NULL argument");
   if (n_sweeps < 0) return set_error(HYB_E_ARG, "negative sweep count");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  const int C = mc->p.n_chains;
-  const size_t smem = sizeof(double) * std::max(mc->p.nmax_ops, 64);
   const int64_t moves = int64_t(n_sweeps) * mc->p.moves_per_sweep;
-  for (int64_t mv = 0; mv < moves; ++mv) {
-    const int64_t step = mc->step;
-    if (mc->mlp) {
-      k_mc_choose<<<C, 64, 0, s>>>(mc->Q, step);
-      MlpActs a = mc->mlp->acts;
-      a.z3 = mc->logits;
-      int rc0 = mlp_forward(mc->mlp, C, mc->X, a, s);
-      if (rc0) return rc0;
+  if (moves > 0) {
+    if (mc->graphs) {
+      if (!mc->gexec || mc->gkey != sweep_key(mc)) {
+        const int rc = capture_sweep(mc);
+        if (rc) return rc;
+      }
+      for (int32_t sw = 0; sw < n_sweeps; ++sw) MC_HIP_TRY(hipGraphLaunch(mc->gexec, s));
+    } else {
+      const int rc = launch_moves(mc, moves, s);
+      if (rc) return rc;
     }
-    k_mc_propose<<<C, 64, 0, s>>>(mc->Q, step);
-    int rc = run_traces(mc, s);
-    if (rc) return rc;
-    const int measure = ((step + 1) % mc->p.meas_every) == 0;
-    k_mc_accept<<<C, 64, smem, s>>>(mc->Q, step, measure);
-    MC_HIP_TRY(hipGetLastError());
-    mc->step = step + 1;
+    mc->step += moves;
   }
   int32_t err = 0;
   MC_HIP_TRY(hipMemcpyAsync(&err, mc->err, sizeof(int32_t), hipMemcpyDeviceToHost, s));
@@ -511,6 +601,13 @@ int hyb_mc_harvest(hyb_mc* mc, int64_t index, void* X, int32_t* targets, void* s
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   k_mc_harvest<<<mc->p.n_chains, 64, 0, s>>>(mc->Q, index, static_cast<__bf16*>(X), targets);
   MC_HIP_TRY(hipGetLastError());
+  return HYB_OK;
+}
+
+int hyb_mc_set_graphs(hyb_mc* mc, int32_t enable) {
+  if (!mc) return set_error(HYB_E_ARG, "NULL argument");
+  mc->graphs = enable != 0;
+  if (!mc->graphs) drop_graph(mc);
   return HYB_OK;
 }
 

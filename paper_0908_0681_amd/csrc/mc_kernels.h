@@ -63,6 +63,7 @@ struct MCParams {
   double* gacc;       // [C][F][n_tau]
   double* meas_sign;  // [C]
   int64_t* n_meas;    // [C]
+  int64_t* step_dev;  // [1] move counter; move `off` of a launch sequence is *step_dev + off
   // learned proposal (learned != 0): features [C][MLP_IN] and logits [C][MLP_OUT]
   int32_t learned;
   double eps_mix;

@@ -391,6 +391,8 @@ int trace_resident(hyb_model* m, int nc, const int64_t* begin, const int64_t* en
   return 0;
 }
 
+int trace_resident_variant(const hyb_model* m) { return m->variant >= 0 ? m->variant : auto_variant(m); }
+
 }  // namespace hyb
 
 using namespace hyb;
@@ -401,6 +403,7 @@ int hyb_model_upload(hyb_model* m, void* stream) {
   if (!m) return set_error(HYB_E_ARG, "NULL model");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   free_device(m);
+  ++m->dev_gen;
   DeviceModel& d = m->dev;
   HIP_TRY(hipGetDevice(&d.device));
   int rc = 0;

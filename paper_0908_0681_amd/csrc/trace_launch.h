@@ -24,4 +24,8 @@ int trace_resident(hyb_model* m, int n_configs, const int64_t* begin, const int6
                    const int16_t* flavor, const int8_t* dagger, int max_ops, double beta, void* ws,
                    double* out_log, int8_t* out_sign, int32_t* err_accum, hipStream_t s);
 
+// The kernel variant trace_resident launches for this model (it changes with
+// hyb_set_trace_variant).
+int trace_resident_variant(const hyb_model* m);
+
 }  // namespace hyb

@@ -103,6 +103,7 @@ _SIGS = {
     "hyb_mc_measure": (C.c_int, [_P, _P, _P, _P]),
     "hyb_mc_reset_measurements": (C.c_int, [_P, _P]),
     "hyb_mc_step_count": (C.c_int, [_P, _P]),
+    "hyb_mc_set_graphs": (C.c_int, [_P, C.c_int32]),
     "hyb_mc_attach_mlp": (C.c_int, [_P, _P, C.c_double]),
     "hyb_mc_harvest": (C.c_int, [_P, C.c_int64, _P, _P, _P]),
     "hyb_mlp_create": (C.c_int, [C.c_uint64, C.POINTER(_P)]),
@@ -454,6 +455,10 @@ class MC:
         s = C.c_int64()
         _check(lib().hyb_mc_step_count(self.h, C.byref(s)))
         return s.value
+
+    def set_graphs(self, enable=True):
+        """Replay each sweep from a captured HIP graph (same chains bit for bit)."""
+        _check(lib().hyb_mc_set_graphs(self.h, 1 if enable else 0))
 
     def attach_mlp(self, mlp, eps=0.1):
         """Learned insertion proposal (mlp: MLP or None for uniform)."""

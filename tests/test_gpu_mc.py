@@ -182,3 +182,71 @@ def test_mc_rejects_bad_input():
     mc.sweep(5)
     assert mc.stats()["moves"] == 10
     mc.close()
+
+
+def _same_chains(a, b):
+    sa, sb = a.state(with_M=True), b.state(with_M=True)
+    for key in ("k", "cre", "ann", "M", "logw", "sign"):
+        assert np.array_equal(sa[key], sb[key]), key
+    for x, y in zip(a.accumulators(), b.accumulators()):
+        assert np.array_equal(x, y)
+    assert a.stats() == b.stats() and a.step_count() == b.step_count()
+
+
+def test_mc_graph_replays_match_direct_launches():
+    """Sweeps replayed from a captured HIP graph (3 moves per sweep) against the same
+    chains launched directly: bitwise equal after every call, with state reads, a
+    measurement reset, a switch to the learned proposal, a training step that
+    reallocates the network's activations (a new capture), and a switch back."""
+    _require_gpu()
+    setup = I.mc_setup(6, 16)
+    w = setup.workload
+    F = 2 * w.params.n_orb
+    o = T.build(w.params, w.retain_window)
+    m = hyb.model_for_workload(w)
+    mk = lambda: hyb.MC(m, setup.n_chains, w.beta, setup.delta, kmax=setup.kmax_flavor, nmax_ops=512,
+                        seed=setup.seed, n_tau=10, meas_every=2, moves_per_sweep=3)
+    direct, graph = mk(), mk()
+    graph.set_graphs(True)
+    start = [(ch.cre, ch.ann) for ch in _oracle_chains(setup, o, F, setup.kmax_flavor)]
+    for x in (direct, graph):
+        x.set_configs(start)
+    net = hyb.MLP(seed=11)
+    for n in (2, 1, 3):
+        direct.sweep(n)
+        graph.sweep(n)
+        _same_chains(direct, graph)
+    for x in (direct, graph):
+        x.reset_measurements()
+        x.attach_mlp(net, 0.2)
+    for n in (2, 1):
+        direct.sweep(n)
+        graph.sweep(n)
+        _same_chains(direct, graph)
+    Xs, Ts = [], []
+    for hv in range(8):
+        X = torch.zeros(setup.n_chains, hyb.MLP_IN, device="cuda", dtype=torch.bfloat16)
+        Tt = torch.zeros(setup.n_chains, 2, device="cuda", dtype=torch.int32)
+        direct.harvest(hv, X, Tt)
+        Xs.append(X)
+        Ts.append(Tt)
+    X, Tt = torch.cat(Xs), torch.cat(Ts)
+    keep = Tt[:, 0] >= 0
+    X, Tt = X[keep].contiguous(), Tt[keep].contiguous()
+    assert X.shape[0] > setup.n_chains   # a batch larger than the chains' grows the activations
+    net.train_step(X, Tt, 1e-2)
+    torch.cuda.synchronize()
+    for n in (2, 2):
+        direct.sweep(n)
+        graph.sweep(n)
+        _same_chains(direct, graph)
+    for x in (direct, graph):
+        x.attach_mlp(None)
+    direct.sweep(3)
+    graph.sweep(3)
+    _same_chains(direct, graph)
+    st = graph.stats()
+    print(f"graph replays: {graph.step_count()} moves per chain, accepted "
+          f"{st['insert_accepted'] + st['remove_accepted']}")
+    direct.close()
+    graph.close()
