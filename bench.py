@@ -28,7 +28,7 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch of the path kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE,
 # scaled by the same counters on a plain 1 GiB device copy (FETCH_SIZE x2.0,
 # WRITE_SIZE x1.0); None once the kernel changes after the counters were taken.
-TRAFFIC = {"kanamori-5orb-b50": 25_047_538.0}
+TRAFFIC = {"kanamori-5orb-b50": 24_981_260.0}
 
 
 def device_batch(batch, torch):
@@ -62,20 +62,22 @@ def measure_workload(k, steps, warmup, torch, hyb, I, dump=""):
         model.trace_batch_device(dbatch, batch.beta, out)
     torch.cuda.synchronize()
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    # HIP events recorded by the library on its own stream around every kernel of the
+    # timed steps; each call returns after its stream drained, so the per-launch
+    # durations are read after every step and averaged over the timed region
+    model.set_timing(True)
+    tsum = [0.0] * 7
     t0 = time.perf_counter()
     start.record()
     for _ in range(steps):
         model.trace_batch_device(dbatch, batch.beta, out)
+        tsum = [a + float(b) for a, b in zip(tsum, model.last_timing())]
     stop.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms = start.elapsed_time(stop)
-    # one instrumented pass: per-launch events around the propagation kernels
-    model.set_timing(True)
-    model.trace_batch_device(dbatch, batch.beta, out)
-    torch.cuda.synchronize()
-    tm = model.last_timing()
     model.set_timing(False)
+    tm = [x / steps for x in tsum]
     vsize = 8 if w.precision == "fp64" else 4
     rowsteps = int(out["rowsteps"].sum().item())
     rows = int(out["rows"].sum().item())
@@ -83,8 +85,8 @@ def measure_workload(k, steps, warmup, torch, hyb, I, dump=""):
     # algorithmic bytes of the propagation kernel: every Lanczos step reads and
     # writes one block vector
     prop_bytes = 2.0 * rowsteps * vsize
-    prop_ms, n_prop = float(tm[3]), int(tm[4])
-    op_ms, n_op = float(tm[5]), int(tm[6])
+    prop_ms, n_prop = float(tm[3]), int(round(tm[4]))
+    op_ms, n_op = float(tm[5]), int(round(tm[6]))
     res = dict(
         workload=w.name, n_configs=batch.n_configs, n_orb=w.params.n_orb, beta=w.beta,
         precision=w.precision, ms_per_step=ms / steps, wall_s=wall,
