@@ -247,6 +247,17 @@ def _sg_half(g, nm, beta, n_tau):
     return SG[:, :, n_tau // 2 - 1:n_tau // 2 + 1].mean(axis=(1, 2))
 
 
+def _robust_var(x):
+    """Variance of a sample from its median absolute deviation, (1.4826 MAD)^2, which
+    equals the variance for normal data and ignores a few outlying values; also the
+    number of values more than 5 such standard deviations from the median."""
+    import numpy as np
+    x = np.asarray(x, dtype=np.float64)
+    med = np.median(x)
+    sd = 1.4826 * np.median(np.abs(x - med))
+    return float(sd * sd), int(np.sum(np.abs(x - med) > 5.0 * sd)) if sd > 0 else 0
+
+
 def _g_blocks(mc, beta, n_tau, n_blocks, moves):
     """Per chain and block: the mean of s*G(beta/2) over each block of moves / n_blocks
     moves, and the chains' totals of s*G and s over all blocks."""
@@ -369,15 +380,21 @@ def measure_ess(torch, hyb, I, harvests=100, train_steps=1000, moves=20000, n_ta
         var_cross = float(np.var(means[ok], ddof=1))
         ess_b = float(ok.sum() * min(var1 / var_block, float(moves))) if var_block > 0 else float("nan")
         ess_c = float(ok.sum() * min(var1 / var_cross, float(moves))) if var_cross > 0 else float("nan")
+        var_rob, n_out = _robust_var(means[ok])
+        ess_r = float(ok.sum() * min(var1 / var_rob, float(moves))) if var_rob > 0 else float("nan")
         ess = ess_c
         out[mode] = {"moves": moves, "wall_s": dt, "ess": ess, "ess_per_s": ess / dt,
                      "ess_cross_chain": ess_c, "ess_blocking": ess_b,
+                     "ess_cross_chain_robust": ess_r, "ess_per_s_robust": ess_r / dt, "outlier_chains": n_out,
                      "acceptance": (s2["insert_accepted"] + s2["remove_accepted"]) / max(1, s2["moves"]),
                      "mean_order": s2["order_sum"] / max(1, s2["moves"]), "sign_avg": s2["sign_sum"] / max(1, s2["moves"]),
                      "g_half": float(np.sum(sg_tot) / np.sum(s_tot))}
     out["var_single"] = var1
     out["headline_estimator"] = "across chains"
     out["learned_over_uniform_ess_per_s"] = out["learned"]["ess_per_s"] / out["uniform"]["ess_per_s"]
+    # the same ratio with the spread of the chain means taken from their median absolute
+    # deviation, so that a few outlying chains do not decide it
+    out["learned_over_uniform_ess_per_s_robust"] = out["learned"]["ess_per_s_robust"] / out["uniform"]["ess_per_s_robust"]
     net.close()
     return out
 

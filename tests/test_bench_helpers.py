@@ -2,6 +2,7 @@
 the depth histogram, and the oracle's feasible-path count (against a brute-force
 walk of the 2-orbital sectors)."""
 import numpy as np
+import pytest
 
 import bench
 from paper_0908_0681_amd import inputs as I
@@ -44,3 +45,14 @@ def test_oracle_feasible_paths_matches_the_full_oracle():
             want += int(o.path(tau, fl, dg, b.beta, r)[0])
     got = bench.oracle_feasible_paths(0)
     assert got == want and got > 0
+
+
+def test_robust_variance_ignores_outlying_chains():
+    rng = np.random.default_rng(3)
+    x = rng.standard_normal(4000) * 2.0
+    v, n = bench._robust_var(x)
+    assert v == pytest.approx(4.0, rel=0.1) and n == 0
+    y = np.concatenate([x, [1e3, -5e2, 80.0]])
+    v2, n2 = bench._robust_var(y)
+    assert v2 == pytest.approx(v, rel=0.01) and n2 == 3
+    assert np.var(y) > 50 * v2
