@@ -136,9 +136,11 @@ int hyb_apply_op(const hyb_model* m, int32_t flavor, int32_t dagger, int32_t blo
 
 /* ---- device parity hooks --------------------------------------------------- */
 
-/* Device operator application (the signed gather of the trace kernels) to n_vec
- * vectors of block block_in.  x: device [n_vec][dim_in], y: device [n_vec][dim_out].
- * Bit-exact: only sign flips and moves. */
+/* Device operator application to n_vec vectors of block block_in, through the
+ * same gather function (gather_op) that the trace kernels apply at every operator
+ * of a path (Sec. III step 4).  x: device [n_vec][dim_in], y: device
+ * [n_vec][dim_out].  Bit-exact: only sign flips and moves.  *block_out = -1 (and y
+ * untouched) when the operator leaves the physical range. */
 int hyb_apply_op_device(hyb_model* m, int32_t flavor, int32_t dagger, int32_t block_in,
                         int32_t n_vec, const double* x, double* y, int32_t* block_out, void* stream);
 
@@ -175,14 +177,16 @@ typedef struct {
 } hyb_trace_out;
 
 /* Evaluates Tr_R for every configuration of the batch (Eq.(2) trace factor;
- * Sec. III steps 3-8): one persistent launch walks all feasible (config,
- * retained state) paths, alternating operator application and Krylov
- * propagation with a running log-norm, then a signed log-sum over R per config.
- * The returned value is the literal operator product in time order (latest
- * operator leftmost) without a time-ordering permutation sign.
+ * Sec. III steps 3-8): a scan finds the feasible (config, retained state)
+ * paths, one workgroup per path then alternates Krylov propagation and operator
+ * application with a running log-norm (all operators of a path in one launch by
+ * default, see hyb_set_chunk), and a last kernel forms the signed log-sum over R
+ * per config.  The returned value is the literal operator product in time order
+ * (latest operator leftmost) without a time-ordering permutation sign.
  * Errors: HYB_E_UNSORTED / HYB_E_FLAVOR for bad configurations (checked on the
  * device; the call synchronises `stream` to read the check), HYB_E_NOCONV if a
- * propagation needs more than 64 substeps, HYB_E_NONFINITE for NaN/Inf. */
+ * propagation needs more than 32 substeps of the depth cap, HYB_E_NONFINITE for
+ * NaN/Inf. */
 int hyb_trace_batch(hyb_model* m, const hyb_config_batch* cfg, double beta,
                     hyb_trace_out* out, void* stream);
 
@@ -258,6 +262,9 @@ typedef struct {
   int32_t n_tau;          /* G(tau) bins */
   int32_t meas_every;     /* measure after every meas_every-th move */
   int32_t moves_per_sweep;
+  int32_t rebuild_every;  /* > 0: M_f = A_f^{-1} is rebuilt from scratch (Gauss-Jordan with partial
+                             pivoting, FP64) after every rebuild_every-th move, bounding the drift of
+                             the O(k^2) updates; 0: never */
 } hyb_mc_params;
 
 typedef struct {
@@ -267,6 +274,8 @@ typedef struct {
   int64_t moves;          /* chain-moves counted */
   double order_sum;       /* sum over chain-moves of the total pair number */
   double sign_sum;        /* sum over chain-moves of sign(w) */
+  double max_drift;       /* largest max|M_f - inv(A_f)| / max|inv(A_f)| found at a rebuild of M
+                             (the accumulated error of the fast updates); 0 before any rebuild */
 } hyb_mc_stats;
 
 typedef struct hyb_mc hyb_mc;
@@ -302,6 +311,27 @@ int hyb_mc_get_accumulators(const hyb_mc* mc, double* gacc, double* meas_sign, i
 int hyb_mc_measure(const hyb_mc* mc, double* G, double* sign_avg, void* stream);
 int hyb_mc_reset_measurements(hyb_mc* mc, void* stream);
 int hyb_mc_step_count(const hyb_mc* mc, int64_t* step);
+
+/* Checkpoint of every chain (the checkpoint/resume of a long run): pair lists, M,
+ * the time-ordered operator lists and weight factors, the move counter (which
+ * keys the Philox counters, so the random stream resumes where it stopped), the
+ * statistics and the G(tau) accumulators.  hyb_mc_save with buf = NULL writes the
+ * size needed to *len; otherwise *len is the buffer size on entry and the bytes
+ * written on return (HYB_E_ARG if too small).  The blob is host memory owned by
+ * the caller; its layout is a fixed header (magic "HYBMCCK1", sizes, beta, seed,
+ * move counter, a hash of the Delta table) followed by the raw arrays.
+ * hyb_mc_load restores a checkpoint into chains created with the same sizes, beta,
+ * seed, Delta table and model precision (else HYB_E_ARG).  It then checks the
+ * stored state: the trace of every stored operator list is evaluated again and
+ * must equal the stored one (1e-8 relative in log for FP64), and A_f^{-1} is
+ * recomputed from the stored times and must equal the stored M (1e-6 relative)
+ * and log|det| (1e-8); a mismatch is HYB_E_ARG.  The stored M itself is kept, so
+ * moves after a load repeat the uninterrupted run bit for bit.  After a load that
+ * failed its checks the chain state is unspecified until a good checkpoint is
+ * loaded or hyb_mc_set_configs is called.  The attached network and the graph
+ * setting are not part of the checkpoint. */
+int hyb_mc_save(const hyb_mc* mc, void* buf, size_t* len, void* stream);
+int hyb_mc_load(hyb_mc* mc, const void* buf, size_t len, void* stream);
 /* enable != 0: hyb_mc_sweep captures one sweep (moves_per_sweep moves of every chain,
  * with no host synchronisation inside) into a HIP graph on first use and replays it
  * n_sweeps times on `stream`.  The move counter lives on the device, so every replay

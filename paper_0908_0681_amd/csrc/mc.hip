@@ -59,6 +59,25 @@ __global__ void k_mc_set_step(int64_t* step, int64_t value, int64_t add) {
   if (threadIdx.x == 0) step[0] = (add ? step[0] : 0) + value;
 }
 
+// Rebuild of M from scratch after every `every`-th move (the kernel reads the move
+// counter, so a captured sweep rebuilds on the same moves as direct launches).
+// every <= 0: unconditional (checkpoint checks and explicit calls).
+__global__ __launch_bounds__(64) void k_mc_rebuild(MCParams Q, int64_t off, int32_t every, int32_t apply, double* ld_f,
+                                                   int32_t* sd_f, double* drift_f, int32_t* err) {
+  __shared__ double a[64 * RB_LD];
+  __shared__ int piv[64];
+  if (every > 0 && ((*Q.step_dev + off + 1) % every) != 0) return;
+  mc_rebuild(Q, blockIdx.x / Q.F, blockIdx.x % Q.F, apply, a, piv, ld_f, sd_f, drift_f, err);
+}
+
+__global__ void k_mc_rebuild_finish(MCParams Q, int64_t off, int32_t every, int32_t apply, const double* ld_f,
+                                    const int32_t* sd_f, const double* drift_f, double* drift, double* ld_out,
+                                    int32_t* sd_out) {
+  if (every > 0 && ((*Q.step_dev + off + 1) % every) != 0) return;
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < Q.n_chains) mc_rebuild_finish(Q, c, apply, ld_f, sd_f, drift_f, drift, ld_out, sd_out);
+}
+
 __global__ __launch_bounds__(64) void k_mc_harvest(MCParams Q, int64_t index, __bf16* X, int32_t* T) {
   mc_harvest(Q, blockIdx.x, index, X, T);
 }
@@ -78,6 +97,12 @@ struct hyb_mc {
   double* t_log = nullptr;
   int8_t* t_sign = nullptr;
   int32_t* err = nullptr;
+  // rebuild of M from scratch: per (chain, flavor) log|det|, sign and drift, and the
+  // largest drift seen per chain
+  double* rb_ld = nullptr;
+  int32_t* rb_sd = nullptr;
+  double* rb_drift_f = nullptr;
+  double* drift = nullptr;
   void* trace_ws = nullptr;
   hyb_mlp* mlp = nullptr;      // learned proposal (NULL: uniform)
   __bf16* X = nullptr;         // [C][MLP_IN] features of the proposing configurations
@@ -182,6 +207,12 @@ int launch_moves(hyb_mc* mc, int64_t moves, hipStream_t s) {
     int rc = run_traces(mc, s);
     if (rc) return rc;
     k_mc_accept<<<C, 64, smem, s>>>(mc->Q, mv, mc->p.meas_every);
+    if (mc->p.rebuild_every > 0) {
+      const int32_t every = mc->p.rebuild_every, apply = 1;
+      k_mc_rebuild<<<C * mc->F, 64, 0, s>>>(mc->Q, mv, every, apply, mc->rb_ld, mc->rb_sd, mc->rb_drift_f, mc->err);
+      k_mc_rebuild_finish<<<(C + 255) / 256, 256, 0, s>>>(mc->Q, mv, every, apply, mc->rb_ld, mc->rb_sd,
+                                                          mc->rb_drift_f, mc->drift, nullptr, nullptr);
+    }
     MC_HIP_TRY(hipGetLastError());
   }
   k_mc_set_step<<<1, 64, 0, s>>>(mc->Q.step_dev, moves, 1);
@@ -201,6 +232,7 @@ std::vector<unsigned char> sweep_key(const hyb_mc* mc) {
   put(&mc->Q, sizeof(mc->Q));
   put(&mc->p.moves_per_sweep, sizeof(mc->p.moves_per_sweep));
   put(&mc->p.meas_every, sizeof(mc->p.meas_every));
+  put(&mc->p.rebuild_every, sizeof(mc->p.rebuild_every));
   put(&mc->mlp, sizeof(mc->mlp));
   if (mc->mlp) {
     put(&mc->mlp->acts, sizeof(mc->mlp->acts));
@@ -241,6 +273,70 @@ int capture_sweep(hyb_mc* mc) {
   return 0;
 }
 
+// ---- checkpoints ------------------------------------------------------------------
+
+struct CkptHeader {
+  char magic[8];  // "HYBMCCK1"
+  int32_t n_chains, F, kmax, nmax_ops, n_tau, n_delta, meas_every, moves_per_sweep, rebuild_every, precision;
+  double beta;
+  uint64_t seed;
+  int64_t step;
+  uint64_t delta_hash;  // FNV-1a over the bytes of the Delta table
+  uint64_t payload;     // bytes after the header
+};
+constexpr char kCkptMagic[8] = {'H', 'Y', 'B', 'M', 'C', 'C', 'K', '1'};
+
+uint64_t fnv1a(const void* p, size_t n) {
+  const unsigned char* b = static_cast<const unsigned char*>(p);
+  uint64_t h = 1469598103934665603ull;
+  for (size_t i = 0; i < n; ++i) {
+    h ^= b[i];
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+// The device arrays of a checkpoint, in file order: the chain state (pair lists,
+// M, the time-ordered operator list, weight factors), the statistics and the
+// measurement accumulators.
+struct CkptField {
+  void* dev;
+  size_t bytes;
+};
+std::vector<CkptField> ckpt_fields(const hyb_mc* mc) {
+  const MCParams& Q = mc->Q;
+  const size_t C = mc->p.n_chains, F = mc->F, KM = mc->p.kmax, NM = mc->p.nmax_ops, NT = mc->p.n_tau;
+  return {{Q.kf, C * F * 4},          {Q.cre, C * F * KM * 8},   {Q.ann, C * F * KM * 8},
+          {Q.M, C * F * KM * KM * 8}, {Q.cur_n, C * 4},          {Q.cur_tau, C * NM * 8},
+          {Q.cur_fl, C * NM * 2},     {Q.cur_dg, C * NM},        {Q.cur_logtr, C * 8},
+          {Q.cur_signtr, C * 4},      {Q.cur_logdet, C * 8},     {Q.cur_signdet, C * 4},
+          {Q.cur_sign, C * 4},        {Q.stats, C * ST_N * 8},   {Q.sign_sum, C * 8},
+          {Q.gacc, C * F * NT * 8},   {Q.meas_sign, C * 8},      {Q.n_meas, C * 8},
+          {mc->drift, C * 8}};
+}
+
+CkptHeader ckpt_header(const hyb_mc* mc) {
+  CkptHeader h{};
+  std::memcpy(h.magic, kCkptMagic, 8);
+  h.n_chains = mc->p.n_chains;
+  h.F = mc->F;
+  h.kmax = mc->p.kmax;
+  h.nmax_ops = mc->p.nmax_ops;
+  h.n_tau = mc->p.n_tau;
+  h.n_delta = mc->p.n_delta;
+  h.meas_every = mc->p.meas_every;
+  h.moves_per_sweep = mc->p.moves_per_sweep;
+  h.rebuild_every = mc->p.rebuild_every;
+  h.precision = mc->m->p.precision;
+  h.beta = mc->p.beta;
+  h.seed = mc->p.seed;
+  h.step = mc->step;
+  h.delta_hash = fnv1a(mc->p.delta, sizeof(double) * (mc->p.n_delta + 1));
+  h.payload = 0;
+  for (const CkptField& f : ckpt_fields(mc)) h.payload += f.bytes;
+  return h;
+}
+
 }  // namespace
 
 extern "C" {
@@ -266,6 +362,7 @@ int hyb_mc_create(hyb_model* m, const hyb_mc_params* p, hyb_mc** out) {
   if (!(p->beta > 0.0) || !std::isfinite(p->beta)) return set_error(HYB_E_ARG, "beta must be positive");
   if (p->n_tau < 1 || p->meas_every < 1 || p->moves_per_sweep < 1)
     return set_error(HYB_E_ARG, "n_tau, meas_every and moves_per_sweep must be >= 1");
+  if (p->rebuild_every < 0) return set_error(HYB_E_ARG, "rebuild_every must be >= 0");
   for (int i = 0; i <= p->n_delta; ++i)
     if (!std::isfinite(p->delta[i])) return set_error(HYB_E_ARG, "non-finite Delta table entry %d", i);
   hyb_mc* mc = new hyb_mc();
@@ -307,7 +404,9 @@ int hyb_mc_create(hyb_model* m, const hyb_mc_params* p, hyb_mc** out) {
       (rc = mc_alloc(mc, mc->t_log, C)) || (rc = mc_alloc(mc, mc->t_sign, C)) ||
       (rc = mc_alloc(mc, Q.stats, size_t(C) * ST_N)) || (rc = mc_alloc(mc, Q.sign_sum, C)) ||
       (rc = mc_alloc(mc, Q.gacc, size_t(C) * F * p->n_tau)) || (rc = mc_alloc(mc, Q.meas_sign, C)) ||
-      (rc = mc_alloc(mc, Q.n_meas, C)) || (rc = mc_alloc(mc, mc->err, 1)) || (rc = mc_alloc(mc, Q.step_dev, 1)))
+      (rc = mc_alloc(mc, Q.n_meas, C)) || (rc = mc_alloc(mc, mc->err, 1)) || (rc = mc_alloc(mc, Q.step_dev, 1)) ||
+      (rc = mc_alloc(mc, mc->rb_ld, size_t(C) * F)) || (rc = mc_alloc(mc, mc->rb_sd, size_t(C) * F)) ||
+      (rc = mc_alloc(mc, mc->rb_drift_f, size_t(C) * F)) || (rc = mc_alloc(mc, mc->drift, C)))
     return fail(rc);
   char* ws = nullptr;
   if ((rc = mc_alloc(mc, ws, trace_ws_bytes(m, C)))) return fail(rc);
@@ -421,6 +520,9 @@ int hyb_mc_set_configs(hyb_mc* mc, const int32_t* k, const double* cre, const do
   MC_HIP_TRY(hipMemcpyAsync(Q.gacc, zerosd.data(), sizeof(double) * C * F * mc->p.n_tau, hipMemcpyHostToDevice, s));
   MC_HIP_TRY(hipMemcpyAsync(Q.meas_sign, zerosd.data(), sizeof(double) * C, hipMemcpyHostToDevice, s));
   MC_HIP_TRY(hipMemcpyAsync(Q.n_meas, zeros64.data(), sizeof(int64_t) * C, hipMemcpyHostToDevice, s));
+  MC_HIP_TRY(hipMemcpyAsync(mc->drift, zerosd.data(), sizeof(double) * C, hipMemcpyHostToDevice, s));
+  // a new state starts without the error of an earlier failed sweep
+  MC_HIP_TRY(hipMemcpyAsync(mc->err, zeros64.data(), sizeof(int32_t), hipMemcpyHostToDevice, s));
   // traces of the initial configurations (through the proposal slots)
   int rc = run_traces(mc, s);
   if (rc) return rc;
@@ -469,8 +571,15 @@ int hyb_mc_sweep(hyb_mc* mc, int32_t n_sweeps, void* stream) {
   int32_t err = 0;
   MC_HIP_TRY(hipMemcpyAsync(&err, mc->err, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   MC_HIP_TRY(hipStreamSynchronize(s));
+  if (err) {
+    // reported once: the flag is cleared so that later calls report their own errors
+    const int32_t zero = 0;
+    MC_HIP_TRY(hipMemcpyAsync(mc->err, &zero, sizeof(int32_t), hipMemcpyHostToDevice, s));
+    MC_HIP_TRY(hipStreamSynchronize(s));
+  }
   if (err & ERR_NOCONV) return set_error(HYB_E_NOCONV, "Krylov propagation failed inside a move");
   if (err & ERR_NONFINITE) return set_error(HYB_E_NONFINITE, "non-finite value inside a move");
+  if (err & ERR_SINGULAR) return set_error(HYB_E_NONFINITE, "singular hybridization matrix at a rebuild of M");
   if (err) return set_error(HYB_E_HIP, "inconsistent proposal (error bits %d)", err);
   return HYB_OK;
 }
@@ -503,11 +612,13 @@ int hyb_mc_get_stats(const hyb_mc* mc, hyb_mc_stats* out, void* stream) {
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const int C = mc->p.n_chains;
   std::vector<int64_t> st(size_t(C) * ST_N);
-  std::vector<double> ss(C);
+  std::vector<double> ss(C), dr(C);
   MC_HIP_TRY(hipMemcpyAsync(st.data(), mc->Q.stats, sizeof(int64_t) * st.size(), hipMemcpyDeviceToHost, s));
   MC_HIP_TRY(hipMemcpyAsync(ss.data(), mc->Q.sign_sum, sizeof(double) * C, hipMemcpyDeviceToHost, s));
+  MC_HIP_TRY(hipMemcpyAsync(dr.data(), mc->drift, sizeof(double) * C, hipMemcpyDeviceToHost, s));
   MC_HIP_TRY(hipStreamSynchronize(s));
   *out = hyb_mc_stats{};
+  for (int c = 0; c < C; ++c) out->max_drift = std::max(out->max_drift, dr[c]);
   for (int c = 0; c < C; ++c) {
     const int64_t* a = st.data() + size_t(c) * ST_N;
     out->insert_proposed += a[ST_INS_PROP];
@@ -608,6 +719,111 @@ int hyb_mc_set_graphs(hyb_mc* mc, int32_t enable) {
   if (!mc) return set_error(HYB_E_ARG, "NULL argument");
   mc->graphs = enable != 0;
   if (!mc->graphs) drop_graph(mc);
+  return HYB_OK;
+}
+
+int hyb_mc_save(const hyb_mc* mc, void* buf, size_t* len, void* stream) {
+  if (!mc || !len) return set_error(HYB_E_ARG, "NULL argument");
+  const CkptHeader h = ckpt_header(mc);
+  const size_t need = sizeof(CkptHeader) + h.payload;
+  if (!buf) {
+    *len = need;
+    return HYB_OK;
+  }
+  if (*len < need) return set_error(HYB_E_ARG, "checkpoint buffer of %zu bytes, %zu needed", *len, need);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  char* out = static_cast<char*>(buf);
+  std::memcpy(out, &h, sizeof h);
+  size_t off = sizeof h;
+  for (const CkptField& f : ckpt_fields(mc)) {
+    MC_HIP_TRY(hipMemcpyAsync(out + off, f.dev, f.bytes, hipMemcpyDeviceToHost, s));
+    off += f.bytes;
+  }
+  MC_HIP_TRY(hipStreamSynchronize(s));
+  *len = need;
+  return HYB_OK;
+}
+
+int hyb_mc_load(hyb_mc* mc, const void* buf, size_t len, void* stream) {
+  if (!mc || !buf) return set_error(HYB_E_ARG, "NULL argument");
+  if (len < sizeof(CkptHeader)) return set_error(HYB_E_ARG, "checkpoint shorter than its header");
+  CkptHeader h;
+  std::memcpy(&h, buf, sizeof h);
+  const CkptHeader mine = ckpt_header(mc);
+  if (std::memcmp(h.magic, kCkptMagic, 8) != 0) return set_error(HYB_E_ARG, "not a chain checkpoint");
+  if (h.n_chains != mine.n_chains || h.F != mine.F || h.kmax != mine.kmax || h.nmax_ops != mine.nmax_ops ||
+      h.n_tau != mine.n_tau || h.n_delta != mine.n_delta || h.beta != mine.beta || h.seed != mine.seed ||
+      h.delta_hash != mine.delta_hash || h.precision != mine.precision || h.payload != mine.payload)
+    return set_error(HYB_E_ARG, "checkpoint of other chains (sizes, beta, seed, bath or precision differ)");
+  if (len < sizeof h + h.payload) return set_error(HYB_E_ARG, "truncated checkpoint");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const int C = mc->p.n_chains, F = mc->F, NM = mc->p.nmax_ops;
+  const char* in = static_cast<const char*>(buf) + sizeof h;
+  for (const CkptField& f : ckpt_fields(mc)) {
+    MC_HIP_TRY(hipMemcpyAsync(f.dev, in, f.bytes, hipMemcpyHostToDevice, s));
+    in += f.bytes;
+  }
+  MCParams& Q = mc->Q;
+  const int32_t zero = 0;
+  MC_HIP_TRY(hipMemcpyAsync(mc->err, &zero, sizeof zero, hipMemcpyHostToDevice, s));
+  k_mc_set_step<<<1, 64, 0, s>>>(Q.step_dev, h.step, 0);
+  MC_HIP_TRY(hipGetLastError());
+  mc->step = h.step;
+  // Consistency: the stored weight factors against a fresh trace of the stored
+  // operator lists and a fresh inverse of the stored pair lists.  The stored M is
+  // kept, so the resumed chains continue bit for bit.
+  MC_HIP_TRY(hipMemcpyAsync(Q.p_tau, Q.cur_tau, sizeof(double) * size_t(C) * NM, hipMemcpyDeviceToDevice, s));
+  MC_HIP_TRY(hipMemcpyAsync(Q.p_fl, Q.cur_fl, sizeof(int16_t) * size_t(C) * NM, hipMemcpyDeviceToDevice, s));
+  MC_HIP_TRY(hipMemcpyAsync(Q.p_dg, Q.cur_dg, sizeof(int8_t) * size_t(C) * NM, hipMemcpyDeviceToDevice, s));
+  std::vector<int32_t> n(C);
+  MC_HIP_TRY(hipMemcpyAsync(n.data(), Q.cur_n, sizeof(int32_t) * C, hipMemcpyDeviceToHost, s));
+  MC_HIP_TRY(hipStreamSynchronize(s));
+  std::vector<int64_t> pend(C);
+  for (int c = 0; c < C; ++c) {
+    if (n[c] < 0 || n[c] > NM) return set_error(HYB_E_ARG, "checkpoint: chain %d has %d operators", c, n[c]);
+    pend[c] = int64_t(c) * NM + n[c];
+  }
+  MC_HIP_TRY(hipMemcpyAsync(Q.p_end, pend.data(), sizeof(int64_t) * C, hipMemcpyHostToDevice, s));
+  int rc = run_traces(mc, s);
+  if (rc) return rc;
+  double* tmp = nullptr;
+  MC_HIP_TRY(hipMalloc(&tmp, sizeof(double) * 2 * C + sizeof(int32_t) * C));
+  double* ld_chk = tmp;
+  double* dr_chk = tmp + C;
+  int32_t* sd_chk = reinterpret_cast<int32_t*>(tmp + 2 * C);
+  MC_HIP_TRY(hipMemsetAsync(dr_chk, 0, sizeof(double) * C, s));
+  k_mc_rebuild<<<C * F, 64, 0, s>>>(Q, 0, 0, 0, mc->rb_ld, mc->rb_sd, mc->rb_drift_f, mc->err);
+  k_mc_rebuild_finish<<<(C + 255) / 256, 256, 0, s>>>(Q, 0, 0, 0, mc->rb_ld, mc->rb_sd, mc->rb_drift_f, dr_chk, ld_chk,
+                                                      sd_chk);
+  std::vector<double> tl(C), lt(C), ld(C), lk(C), dr(C);
+  std::vector<int8_t> ts(C);
+  std::vector<int32_t> st(C), sd(C), sk(C);
+  int32_t err = 0;
+  hipError_t e = hipSuccess;
+  auto d2h = [&](void* dst, const void* src, size_t bytes) {
+    if (e == hipSuccess) e = hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s);
+  };
+  d2h(tl.data(), mc->t_log, sizeof(double) * C);
+  d2h(ts.data(), mc->t_sign, sizeof(int8_t) * C);
+  d2h(lt.data(), Q.cur_logtr, sizeof(double) * C);
+  d2h(st.data(), Q.cur_signtr, sizeof(int32_t) * C);
+  d2h(ld.data(), Q.cur_logdet, sizeof(double) * C);
+  d2h(sd.data(), Q.cur_signdet, sizeof(int32_t) * C);
+  d2h(lk.data(), ld_chk, sizeof(double) * C);
+  d2h(sk.data(), sd_chk, sizeof(int32_t) * C);
+  d2h(dr.data(), dr_chk, sizeof(double) * C);
+  d2h(&err, mc->err, sizeof(int32_t));
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(tmp);
+  if (e != hipSuccess) return set_error(HYB_E_HIP, "checkpoint check: %s", hipGetErrorString(e));
+  if (err) return set_error(HYB_E_ARG, "checkpoint: trace or determinant of the stored state failed (bits %d)", err);
+  const double tol_tr = (mc->m->p.precision == HYB_FP64) ? 1e-8 : 1e-4;
+  for (int c = 0; c < C; ++c) {
+    if (ts[c] != st[c] || !(std::fabs(tl[c] - lt[c]) <= tol_tr * std::max(1.0, std::fabs(lt[c]))))
+      return set_error(HYB_E_ARG, "checkpoint: chain %d stored trace disagrees with its operators", c);
+    if (sk[c] != sd[c] || !(std::fabs(lk[c] - ld[c]) <= 1e-8 * std::max(1.0, std::fabs(ld[c]))) || !(dr[c] <= 1e-6))
+      return set_error(HYB_E_ARG, "checkpoint: chain %d stored M / determinant disagree with its times", c);
+  }
   return HYB_OK;
 }
 

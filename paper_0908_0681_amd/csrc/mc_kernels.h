@@ -500,6 +500,133 @@ __device__ inline void mc_accept(const MCParams& Q, int c, int64_t step, int mea
   }
 }
 
+// ---- rebuild of M from scratch ---------------------------------------------------
+
+constexpr int RB_LD = 65;  // LDS row stride of the rebuild (64 columns + 1 against bank conflicts)
+
+// One wavefront per (chain c, flavor f): A_f from the chain's current times, its
+// inverse by Gauss-Jordan elimination with partial pivoting (lane r owns row r),
+// log|det A_f| and its sign.  The relative drift max|M_f - inv(A_f)| / max|inv(A_f)|
+// of the incrementally updated M_f goes to drift_f[c][f], the log-determinant and
+// sign to ld_f / sd_f.  apply != 0 replaces M_f by the fresh inverse.  A singular
+// A_f (no nonzero pivot) sets ERR_SINGULAR and leaves M_f alone.
+// a: LDS scratch of 64 * RB_LD doubles; piv: LDS scratch of 64 ints.
+__device__ inline void mc_rebuild(const MCParams& Q, int c, int f, int apply, double* a, int* piv, double* ld_f,
+                                  int32_t* sd_f, double* drift_f, int32_t* err) {
+  const int lane = threadIdx.x;
+  const int F = Q.F, KM = Q.kmax;
+  const int k = Q.kf[c * F + f];
+  const double* cre = Q.cre + (int64_t(c) * F + f) * KM;
+  const double* ann = Q.ann + (int64_t(c) * F + f) * KM;
+  double* Mf = Q.M + (int64_t(c) * F + f) * KM * KM;
+  if (lane < k)
+    for (int j = 0; j < k; ++j) a[lane * RB_LD + j] = delta_at(Q, __dadd_rn(cre[lane], -ann[j]));
+  __syncthreads();
+  double logdet = 0.0;
+  int sg = 1;
+  bool singular = false;
+  for (int col = 0; col < k; ++col) {
+    // every lane scans the same column, so the pivot choice is uniform
+    int p = col;
+    double best = fabs(a[col * RB_LD + col]);
+    for (int r = col + 1; r < k; ++r) {
+      const double v = fabs(a[r * RB_LD + col]);
+      if (v > best) {
+        best = v;
+        p = r;
+      }
+    }
+    if (!(best > 0.0)) {
+      singular = true;
+      break;
+    }
+    __syncthreads();
+    if (p != col && lane < k) {
+      const double t = a[col * RB_LD + lane];
+      a[col * RB_LD + lane] = a[p * RB_LD + lane];
+      a[p * RB_LD + lane] = t;
+    }
+    if (lane == 0) piv[col] = p;
+    __syncthreads();
+    const double d = a[col * RB_LD + col];
+    logdet += log(fabs(d));
+    if (d < 0.0) sg = -sg;
+    if (p != col) sg = -sg;
+    __syncthreads();
+    // pivot row: a[col][j] / d, with the pivot position becoming 1 / d
+    if (lane < k) a[col * RB_LD + lane] = ((lane == col) ? 1.0 : a[col * RB_LD + lane]) / d;
+    __syncthreads();
+    // other rows: a[r][j] -= a[r][col] * a[col][j], the pivot column becoming -a[r][col] / d
+    if (lane < k && lane != col) {
+      const double fct = a[lane * RB_LD + col];
+      a[lane * RB_LD + col] = 0.0;
+      for (int j = 0; j < k; ++j) a[lane * RB_LD + j] = __dadd_rn(a[lane * RB_LD + j], -__dmul_rn(fct, a[col * RB_LD + j]));
+    }
+    __syncthreads();
+  }
+  if (singular) {
+    if (lane == 0) {
+      atomicOr(err, ERR_SINGULAR);
+      ld_f[c * F + f] = 0.0;
+      sd_f[c * F + f] = 0;
+      drift_f[c * F + f] = 0.0;
+    }
+    return;
+  }
+  // the row swaps of the elimination become column swaps of the inverse, undone in
+  // reverse order
+  for (int col = k - 1; col >= 0; --col) {
+    const int p = piv[col];
+    if (p != col && lane < k) {
+      const double t = a[lane * RB_LD + col];
+      a[lane * RB_LD + col] = a[lane * RB_LD + p];
+      a[lane * RB_LD + p] = t;
+    }
+  }
+  __syncthreads();
+  double dmax = 0.0, amax = 0.0;
+  if (lane < k)
+    for (int j = 0; j < k; ++j) {
+      const double v = a[lane * RB_LD + j];
+      amax = fmax(amax, fabs(v));
+      dmax = fmax(dmax, fabs(v - Mf[lane * KM + j]));
+    }
+  for (int o = 32; o >= 1; o >>= 1) {
+    amax = fmax(amax, shfl_xor_d(amax, o));
+    dmax = fmax(dmax, shfl_xor_d(dmax, o));
+  }
+  if (apply && lane < k)
+    for (int j = 0; j < k; ++j) Mf[lane * KM + j] = a[lane * RB_LD + j];
+  if (lane == 0) {
+    ld_f[c * F + f] = logdet;
+    sd_f[c * F + f] = sg;
+    drift_f[c * F + f] = (amax > 0.0) ? dmax / amax : 0.0;
+  }
+}
+
+// Per chain, after mc_rebuild of all its flavors: log|det| summed over the flavors
+// in flavor order, the largest flavor drift folded into drift[c], and with
+// apply != 0 the chain's determinant state replaced (the weight's sign follows a
+// changed determinant sign).
+__device__ inline void mc_rebuild_finish(const MCParams& Q, int c, int apply, const double* ld_f, const int32_t* sd_f,
+                                         const double* drift_f, double* drift, double* ld_out, int32_t* sd_out) {
+  double ld = 0.0, dr = 0.0;
+  int sd = 1;
+  for (int g = 0; g < Q.F; ++g) {
+    ld += ld_f[c * Q.F + g];
+    sd *= sd_f[c * Q.F + g];
+    dr = fmax(dr, drift_f[c * Q.F + g]);
+  }
+  drift[c] = fmax(drift[c], dr);
+  if (ld_out) ld_out[c] = ld;
+  if (sd_out) sd_out[c] = sd;
+  if (apply && sd != 0) {
+    Q.cur_sign[c] = Q.cur_sign[c] * Q.cur_signdet[c] * sd;
+    Q.cur_signdet[c] = sd;
+    Q.cur_logdet[c] = ld;
+  }
+}
+
 // One training sample per chain: a flavor with pairs (uniform among them), one of
 // its k^2 (creator, annihilator) pairs (uniform), the features of the configuration
 // without that pair, and the targets (bin of tau_s, bin of l) on 64 bins.  Chains

@@ -164,30 +164,49 @@ static int grow(hyb_mlp* p, int Bn) { return mlp_ensure(p, Bn); }
 
 int mlp_ensure(hyb_mlp* p, int Bn) {
   if (Bn <= p->cap) return 0;
-  for (void* q : p->act_allocs) (void)hipFree(q);
-  p->act_allocs.clear();
+  // every new buffer is allocated before any old one is released: on failure the
+  // network keeps its old buffers and capacity, and nothing allocated here leaks
+  std::vector<void*> fresh;
+  bool ok = true;
   auto alloc = [&](size_t bytes) -> void* {
     void* q = nullptr;
-    if (hipMalloc(&q, bytes) != hipSuccess) return nullptr;
-    p->act_allocs.push_back(q);
+    if (!ok || hipMalloc(&q, bytes) != hipSuccess) {
+      ok = false;
+      return nullptr;
+    }
+    fresh.push_back(q);
     return q;
   };
   const size_t B = size_t(Bn);
-  MlpActs& a = p->acts;
+  MlpActs a{};
   a.z1 = static_cast<float*>(alloc(B * MLP_H * 4));
   a.z2 = static_cast<float*>(alloc(B * MLP_H * 4));
   a.z3 = static_cast<float*>(alloc(B * MLP_OUT * 4));
   a.h1 = static_cast<__bf16*>(alloc(B * MLP_H * 2));
   a.h2 = static_cast<__bf16*>(alloc(B * MLP_H * 2));
-  p->dz3 = static_cast<float*>(alloc(B * MLP_OUT * 4));
-  p->dz2 = static_cast<float*>(alloc(B * MLP_H * 4));
-  p->dz1 = static_cast<float*>(alloc(B * MLP_H * 4));
-  p->dz3b = static_cast<__bf16*>(alloc(B * MLP_OUT * 2));
-  p->dz2b = static_cast<__bf16*>(alloc(B * MLP_H * 2));
-  p->dz1b = static_cast<__bf16*>(alloc(B * MLP_H * 2));
-  p->loss = static_cast<float*>(alloc(B * 4));
-  for (void* q : p->act_allocs)
-    if (!q) return set_error(HYB_E_OOM, "MLP activations for batch %d", Bn);
+  float* dz3 = static_cast<float*>(alloc(B * MLP_OUT * 4));
+  float* dz2 = static_cast<float*>(alloc(B * MLP_H * 4));
+  float* dz1 = static_cast<float*>(alloc(B * MLP_H * 4));
+  __bf16* dz3b = static_cast<__bf16*>(alloc(B * MLP_OUT * 2));
+  __bf16* dz2b = static_cast<__bf16*>(alloc(B * MLP_H * 2));
+  __bf16* dz1b = static_cast<__bf16*>(alloc(B * MLP_H * 2));
+  float* loss = static_cast<float*>(alloc(B * 4));
+  if (!ok) {
+    for (void* q : fresh) (void)hipFree(q);
+    return set_error(HYB_E_OOM, "MLP activations for batch %d", Bn);
+  }
+  // work already queued on the old buffers must finish before they are released
+  MLP_HIP_TRY(hipDeviceSynchronize());
+  for (void* q : p->act_allocs) (void)hipFree(q);
+  p->act_allocs = fresh;
+  p->acts = a;
+  p->dz3 = dz3;
+  p->dz2 = dz2;
+  p->dz1 = dz1;
+  p->dz3b = dz3b;
+  p->dz2b = dz2b;
+  p->dz1b = dz1b;
+  p->loss = loss;
   p->cap = Bn;
   return 0;
 }
@@ -327,6 +346,11 @@ int hyb_mlp_set_weights(hyb_mlp* p, const float* w, const float* b) {
     MLP_HIP_TRY(hipMemcpy(p->w[L], w + ow, size_t(kWSize[L]) * 4, hipMemcpyHostToDevice));
     MLP_HIP_TRY(hipMemcpy(p->bias[L], b + ob, size_t(kBSize[L]) * 4, hipMemcpyHostToDevice));
     k_to_bf16<<<(kWSize[L] + 255) / 256, 256>>>(kWSize[L], p->w[L], p->wb[L]);
+    // Adam starts over: first and second moments back to zero with the step count
+    MLP_HIP_TRY(hipMemset(p->m1[L], 0, size_t(kWSize[L]) * 4));
+    MLP_HIP_TRY(hipMemset(p->m2[L], 0, size_t(kWSize[L]) * 4));
+    MLP_HIP_TRY(hipMemset(p->bm1[L], 0, size_t(kBSize[L]) * 4));
+    MLP_HIP_TRY(hipMemset(p->bm2[L], 0, size_t(kBSize[L]) * 4));
     ow += kWSize[L];
     ob += kBSize[L];
   }

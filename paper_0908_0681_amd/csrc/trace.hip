@@ -1,5 +1,6 @@
-// Device side of libhyb: model upload, the batched trace (scan -> persistent
-// trace kernel -> signed log-sum), device parity hooks and kernel variants.
+// Device side of libhyb: model upload, the batched trace (scan -> path kernels,
+// one workgroup per feasible path -> signed log-sum), device parity hooks and
+// kernel variants.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -96,22 +97,14 @@ __global__ void k_reduce(TraceParams P, double* out_log, int8_t* out_sign, int32
     reduce_config(P, c, out_log, out_sign, out_steps, out_sub, out_feas, out_rowsteps, out_rows);
 }
 
-// Operator application on a batch of vectors (parity hook).
+// Operator application on a batch of vectors (parity hook): the trace kernels'
+// own gather (gather_op), one thread per output component.
 __global__ void k_apply_op(const uint32_t* states, const int32_t* rank, BlockDev Bin, BlockDev Bout, int f,
                            int dagger, int n_vec, const double* x, double* y) {
   const int64_t id = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (id >= int64_t(n_vec) * Bout.dim) return;
   const int v = int(id / Bout.dim), r = int(id - int64_t(v) * Bout.dim);
-  const uint32_t bit = 1u << f;
-  const uint32_t t = states[Bout.state_off + r];
-  const bool has = dagger ? ((t & bit) != 0u) : ((t & bit) == 0u);
-  double val = 0.0;
-  if (has) {
-    const uint32_t s = t ^ bit;
-    const double src = x[int64_t(v) * Bin.dim + rank[s]];
-    val = (__popc(s & (bit - 1u)) & 1) ? -src : src;
-  }
-  y[id] = val;
+  y[id] = gather_op<double>(states, rank, Bout, r, f, dagger, x + int64_t(v) * Bin.dim);
 }
 
 // Krylov propagation of a batch of vectors of one block (parity hook): one
@@ -340,23 +333,13 @@ size_t trace_ws_bytes(const hyb_model* m, int n_configs) {
   return resident_layout(m, n_configs, sizeof(double)).total;
 }
 
-int trace_resident(hyb_model* m, int nc, const int64_t* begin, const int64_t* ends, const double* tau,
-                   const int16_t* flavor, const int8_t* dagger, int max_ops, double beta, void* ws,
-                   double* out_log, int8_t* out_sign, int32_t* err_accum, hipStream_t s) {
-  const int vi = m->variant >= 0 ? m->variant : auto_variant(m);
-  const Variant& V = kVariants[vi];
-  const ResidentLayout L = resident_layout(m, nc, V.fp64 ? sizeof(double) : sizeof(float));
-  const int64_t npairs = int64_t(nc) * int64_t(m->ret_block.size());
+// Workspace pointers of a device-resident launch for nc configurations at ws.
+static TraceParams resident_params(const hyb_model* m, int nc, void* ws, size_t vbytes) {
+  const ResidentLayout L = resident_layout(m, nc, vbytes);
   char* w = static_cast<char*>(ws);
   TraceParams P = base_params(m);
   P.n_configs = nc;
-  P.n_pairs = int32_t(npairs);
-  P.beta = beta;
-  P.offsets = begin;
-  P.ends = ends;
-  P.tau = tau;
-  P.flavor = flavor;
-  P.dagger = dagger;
+  P.n_pairs = int32_t(int64_t(nc) * int64_t(m->ret_block.size()));
   P.counters = reinterpret_cast<int32_t*>(w + L.cnt);
   P.work = reinterpret_cast<int32_t*>(w + L.work);
   P.p_sign = reinterpret_cast<int8_t*>(w + L.psign);
@@ -374,6 +357,17 @@ int trace_resident(hyb_model* m, int nc, const int64_t* begin, const int64_t* en
   P.st_ell = reinterpret_cast<double*>(w + L.sell);
   P.st_vec = w + L.svec;
   P.vstride = (m->max_dim + 63) & ~63;
+  return P;
+}
+
+// Scan, path kernels with grids sized for every (configuration, retained state)
+// pair (workgroups past the queued paths return at once), then the signed log-sum.
+// No host synchronisation; the counters are cleared by a kernel, so the sequence
+// may be captured.  Optional outputs may be NULL.
+static int resident_launch(const Variant& V, TraceParams& P, int max_ops, double* out_log, int8_t* out_sign,
+                           int32_t* out_steps, int32_t* out_sub, int32_t* out_feas, int64_t* out_rs, int64_t* out_rw,
+                           hipStream_t s) {
+  const int64_t npairs = P.n_pairs;
   k_init_counters<<<1, 64, 0, s>>>(P.counters);
   const int scan_threads = 256;
   k_scan<<<unsigned((npairs + scan_threads - 1) / scan_threads), scan_threads, 0, s>>>(P);
@@ -385,7 +379,25 @@ int trace_resident(hyb_model* m, int nc, const int64_t* begin, const int64_t* en
     HIP_TRY(hipLaunchKernel(V.chunk_fn, dim3(unsigned(npairs)), dim3(V.nt), ak, 0, s));
     HIP_TRY(hipLaunchKernel(V.final_fn, dim3(unsigned(npairs)), dim3(V.nt), a0, 0, s));
   }
-  k_reduce<<<(nc + 255) / 256, 256, 0, s>>>(P, out_log, out_sign, nullptr, nullptr, nullptr, nullptr, nullptr);
+  k_reduce<<<(P.n_configs + 255) / 256, 256, 0, s>>>(P, out_log, out_sign, out_steps, out_sub, out_feas, out_rs, out_rw);
+  HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+int trace_resident(hyb_model* m, int nc, const int64_t* begin, const int64_t* ends, const double* tau,
+                   const int16_t* flavor, const int8_t* dagger, int max_ops, double beta, void* ws,
+                   double* out_log, int8_t* out_sign, int32_t* err_accum, hipStream_t s) {
+  const int vi = m->variant >= 0 ? m->variant : auto_variant(m);
+  const Variant& V = kVariants[vi];
+  TraceParams P = resident_params(m, nc, ws, V.fp64 ? sizeof(double) : sizeof(float));
+  P.beta = beta;
+  P.offsets = begin;
+  P.ends = ends;
+  P.tau = tau;
+  P.flavor = flavor;
+  P.dagger = dagger;
+  const int rc = resident_launch(V, P, max_ops, out_log, out_sign, nullptr, nullptr, nullptr, nullptr, nullptr, s);
+  if (rc) return rc;
   k_fold_errors<<<1, 64, 0, s>>>(P.counters, err_accum);
   HIP_TRY(hipGetLastError());
   return 0;

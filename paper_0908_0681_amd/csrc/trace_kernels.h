@@ -1,13 +1,14 @@
 // Device code of the Krylov trace (gfx950, wave64).
 //
-// The trace is evaluated step-synchronously over all feasible (configuration,
-// retained state) paths of a batch: one launch applies operator k to every path
-// whose configuration has an operator k, one launch propagates every such path
-// over the next interval.  Between launches a path's state (block, log-scale,
-// unit vector) lives in HBM.  Inside a propagation one workgroup owns one path:
-// the vector lives in registers, RPT rows per thread (row = tid + k*NT), the
-// Lanczos basis V_0..V_m lives in registers too, and LDS holds the vector being
-// gathered by the SpMV, the reduction partials and the small tridiagonal problem.
+// One workgroup carries one feasible (configuration, retained state) path through
+// all of its operators in one launch (k_path_chunk with the whole operator range;
+// shorter chunks, down to one operator per launch, give the same arithmetic in
+// another launch schedule).  Between operators a path's state (block, log-scale,
+// unit vector) passes through global memory.  Inside a propagation the vector
+// lives in registers, RPT rows per thread (row = tid + k*NT), the Lanczos basis
+// V_0..V_m lives in registers too, and LDS holds the vector being gathered by the
+// SpMV, the block's off-diagonal rows, the reduction partials and the small
+// tridiagonal problem.
 //
 // Steps (Sec. III): the retained eigenstate enters with the scalar phase of the
 // two edge intervals (step 3); each operator is a signed gather between blocks
@@ -24,7 +25,7 @@
 
 namespace hyb {
 
-enum : int32_t { ERR_UNSORTED = 1, ERR_FLAVOR = 2, ERR_NOCONV = 4, ERR_NONFINITE = 8 };
+enum : int32_t { ERR_UNSORTED = 1, ERR_FLAVOR = 2, ERR_NOCONV = 4, ERR_NONFINITE = 8, ERR_SINGULAR = 16 };
 
 struct TraceParams {
   // model
@@ -372,37 +373,6 @@ struct PathEngine {
       }
     }
     return staged;
-  }
-
-  // x <- O x with O = c_f (dagger 0) or c_f^dag (dagger 1), block B -> Bt.
-  // Returns the squared norm of the result.
-  __device__ __forceinline__ double apply_op(const BlockDev& B, const BlockDev& Bt, int f, int dagger,
-                                             VT (&x)[RPT]) {
-#pragma unroll
-    for (int k = 0; k < RPT; ++k)
-      if (row(k) < B.dim) S.vec[row(k)] = x[k];
-    __syncthreads();
-    const uint32_t bit = 1u << f;
-    double nrm = 0.0;
-#pragma unroll
-    for (int k = 0; k < RPT; ++k) {
-      const int r = row(k);
-      VT val = VT(0);
-      if (r < Bt.dim) {
-        const uint32_t t = P.states[Bt.state_off + r];
-        // source state s with O|s> ~ |t>: creator needs bit f set in t, annihilator unset
-        const bool has = dagger ? ((t & bit) != 0u) : ((t & bit) == 0u);
-        if (has) {
-          const uint32_t s = t ^ bit;
-          const VT src = S.vec[P.rank[s]];
-          val = (__popc(s & (bit - 1u)) & 1) ? -src : src;
-        }
-      }
-      x[k] = val;
-      nrm += to_d(val) * to_d(val);
-    }
-    __syncthreads();  // S.vec may be rewritten right after
-    return block_sum1(nrm);
   }
 
   // Eigendecomposition of the m x m symmetric tridiagonal T_m = (alpha, beta) of this
@@ -1150,6 +1120,23 @@ __device__ inline void path_init(const TraceParams& P, int w) {
   }
 }
 
+// Component r of O x in the target block Bt, for O = c_f (dg = 0) or c_f^dag
+// (dg = 1) and x a vector of the source block (indexed by in-block rank): the
+// source state s with O|s> ~ |t> is t with bit f flipped (a creator needs bit f set
+// in t, an annihilator needs it clear), and the Jordan-Wigner sign is the parity
+// of the occupied flavors below f.  Only moves and sign flips: bit-exact.
+template <typename VT>
+__device__ __forceinline__ VT gather_op(const uint32_t* states, const int32_t* rank, const BlockDev& Bt, int r,
+                                        int f, int dg, const VT* x) {
+  const uint32_t bit = 1u << f;
+  const uint32_t t = states[Bt.state_off + r];
+  const bool has = dg ? ((t & bit) != 0u) : ((t & bit) == 0u);
+  if (!has) return VT(0);
+  const uint32_t s = t ^ bit;
+  const VT v = x[rank[s]];
+  return (__popc(s & (bit - 1u)) & 1) ? -v : v;
+}
+
 // Step 4: operator k of the path's configuration, a signed gather from block b to
 // the target block, then renormalisation with the log of the norm kept in ell.
 template <typename VT, int NT, int RPT>
@@ -1172,23 +1159,12 @@ __device__ inline void path_op(const TraceParams& P, int w, int k, double* red) 
   const BlockDev Bt = P.blocks[bt];
   const VT* src = path_vec<VT>(P, k & 1, w);
   VT* dst = path_vec<VT>(P, (k + 1) & 1, w);
-  const uint32_t bit = 1u << f;
   VT val[RPT];
   double part = 0.0;
 #pragma unroll
   for (int q = 0; q < RPT; ++q) {
     const int r = threadIdx.x + q * NT;
-    VT v = VT(0);
-    if (r < Bt.dim) {
-      const uint32_t t = P.states[Bt.state_off + r];
-      // source state s with O|s> ~ |t>: a creator needs bit f set in t, an annihilator unset
-      const bool has = dg ? ((t & bit) != 0u) : ((t & bit) == 0u);
-      if (has) {
-        const uint32_t s = t ^ bit;
-        const VT x = src[P.rank[s]];
-        v = (__popc(s & (bit - 1u)) & 1) ? -x : x;
-      }
-    }
+    const VT v = (r < Bt.dim) ? gather_op<VT>(P.states, P.rank, Bt, r, f, dg, src) : VT(0);
     val[q] = v;
     part += to_d(v) * to_d(v);
   }

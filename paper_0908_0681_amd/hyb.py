@@ -56,14 +56,14 @@ class McParamsC(C.Structure):
     _fields_ = [("n_chains", C.c_int32), ("beta", C.c_double), ("n_delta", C.c_int32),
                 ("delta", C.POINTER(C.c_double)), ("kmax", C.c_int32), ("nmax_ops", C.c_int32),
                 ("seed", C.c_uint64), ("n_tau", C.c_int32), ("meas_every", C.c_int32),
-                ("moves_per_sweep", C.c_int32)]
+                ("moves_per_sweep", C.c_int32), ("rebuild_every", C.c_int32)]
 
 
 class McStatsC(C.Structure):
     _fields_ = [("insert_proposed", C.c_int64), ("insert_accepted", C.c_int64),
                 ("remove_proposed", C.c_int64), ("remove_accepted", C.c_int64),
                 ("impossible", C.c_int64), ("zero_weight", C.c_int64), ("moves", C.c_int64),
-                ("order_sum", C.c_double), ("sign_sum", C.c_double)]
+                ("order_sum", C.c_double), ("sign_sum", C.c_double), ("max_drift", C.c_double)]
 
 
 # name -> (restype, argtypes)
@@ -104,6 +104,8 @@ _SIGS = {
     "hyb_mc_reset_measurements": (C.c_int, [_P, _P]),
     "hyb_mc_step_count": (C.c_int, [_P, _P]),
     "hyb_mc_set_graphs": (C.c_int, [_P, C.c_int32]),
+    "hyb_mc_save": (C.c_int, [_P, _P, C.POINTER(C.c_size_t), _P]),
+    "hyb_mc_load": (C.c_int, [_P, _P, C.c_size_t, _P]),
     "hyb_mc_attach_mlp": (C.c_int, [_P, _P, C.c_double]),
     "hyb_mc_harvest": (C.c_int, [_P, C.c_int64, _P, _P, _P]),
     "hyb_mlp_create": (C.c_int, [C.c_uint64, C.POINTER(_P)]),
@@ -324,8 +326,8 @@ class Model:
         _log("trace_batch done")
         return res
 
-    def trace_batch_device(self, dev_batch, beta, out, stream=None):
-        """dev_batch / out: dicts of torch device tensors (see bench.py)."""
+    @staticmethod
+    def _device_args(dev_batch, out):
         cfg = ConfigBatchC(n_configs=dev_batch["offsets"].numel() - 1, offsets=_ptr(dev_batch["offsets"]),
                            tau=_ptr(dev_batch["tau"]), flavor=_ptr(dev_batch["flavor"]),
                            dagger=_ptr(dev_batch["dagger"]), on_device=1)
@@ -333,6 +335,11 @@ class Model:
                       krylov_steps=_ptr(out.get("krylov_steps")), substeps=_ptr(out.get("substeps")),
                       feasible_paths=_ptr(out.get("feasible_paths")), rowsteps=_ptr(out.get("rowsteps")),
                       rows=_ptr(out.get("rows")), on_device=1)
+        return cfg, o
+
+    def trace_batch_device(self, dev_batch, beta, out, stream=None):
+        """dev_batch / out: dicts of torch device tensors (see bench.py)."""
+        cfg, o = self._device_args(dev_batch, out)
         _check(lib().hyb_trace_batch(self.h, C.byref(cfg), beta, C.byref(o), _stream(stream)))
 
     def block_spmm(self, b, X, Y, n_vec, stream=None):
@@ -378,14 +385,14 @@ class MC:
     """Monte Carlo chains on the model's device (hyb_mc_*)."""
 
     def __init__(self, model: Model, n_chains, beta, delta, kmax=48, nmax_ops=1024, seed=7, n_tau=200,
-                 meas_every=1, moves_per_sweep=1):
+                 meas_every=1, moves_per_sweep=1, rebuild_every=1000):
         self.model = model
         self.delta = np.ascontiguousarray(delta, dtype=np.float64)
         self.n_chains, self.beta, self.kmax, self.n_tau = int(n_chains), float(beta), int(kmax), int(n_tau)
         self.F = model.info()["n_flavors"]
         p = McParamsC(self.n_chains, self.beta, len(self.delta) - 1,
                       self.delta.ctypes.data_as(C.POINTER(C.c_double)), self.kmax, int(nmax_ops),
-                      int(seed), self.n_tau, int(meas_every), int(moves_per_sweep))
+                      int(seed), self.n_tau, int(meas_every), int(moves_per_sweep), int(rebuild_every))
         h = _P()
         _check(lib().hyb_mc_create(model.h, C.byref(p), C.byref(h)))
         self.h = h
@@ -455,6 +462,19 @@ class MC:
         s = C.c_int64()
         _check(lib().hyb_mc_step_count(self.h, C.byref(s)))
         return s.value
+
+    def save(self, stream=None) -> bytes:
+        """Checkpoint of every chain (hyb_mc_save) as bytes."""
+        n = C.c_size_t()
+        _check(lib().hyb_mc_save(self.h, None, C.byref(n), _stream(stream)))
+        buf = C.create_string_buffer(n.value)
+        _check(lib().hyb_mc_save(self.h, buf, C.byref(n), _stream(stream)))
+        return buf.raw[: n.value]
+
+    def load(self, blob: bytes, stream=None):
+        """Restores a checkpoint written by save() (hyb_mc_load)."""
+        buf = C.create_string_buffer(blob, len(blob))
+        _check(lib().hyb_mc_load(self.h, buf, len(blob), _stream(stream)))
 
     def set_graphs(self, enable=True):
         """Replay each sweep from a captured HIP graph (same chains bit for bit)."""

@@ -208,6 +208,13 @@ def workload(k: int) -> Workload:
 # bath and Monte Carlo inputs
 # --------------------------------------------------------------------------
 
+def parity_sample(n_configs: int, n: int, seed: int) -> np.ndarray:
+    """Sorted indices of n of the n_configs configurations of a batch, drawn without
+    replacement (the seeded sample a parity check evaluates)."""
+    rng = np.random.default_rng(seed)
+    return np.sort(rng.choice(n_configs, n, replace=False))
+
+
 def semicircle_delta(beta: float, n_tau: int, D: float = 2.0, t: float = 1.0,
                      n_quad: int = 6000) -> np.ndarray:
     """Hybridization function of a semicircular bath, tabulated on a uniform grid.

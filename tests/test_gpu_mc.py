@@ -20,6 +20,7 @@ import pytest
 from paper_0908_0681_amd import inputs as I
 from paper_0908_0681_amd import hyb
 from oracle import mc as MC
+from oracle import pool as OP
 from oracle import trace as T
 
 pytestmark = pytest.mark.gpu
@@ -50,48 +51,45 @@ def _oracle_chains(setup, o, F, kmax):
     return chains
 
 
-def _replay_and_compare(which, n_chains, n_moves, kmax=None, n_tau=20, meas_every=3, empty_start=False):
+def _replay_and_compare(which, n_chains, n_moves, kmax=None, n_tau=20, meas_every=3, empty_start=False,
+                        rebuild_every=1000):
+    """Device chains against the oracle's chains (replayed on a process pool), move by
+    move with the same uniforms; returns the number of accepted moves."""
     _require_gpu()
     setup = I.mc_setup(which, n_chains)
     w = setup.workload
     kmax = kmax or setup.kmax_flavor
     F = 2 * w.params.n_orb
-    o = T.build(w.params, w.retain_window)
     m = hyb.model_for_workload(w)
     mc = hyb.MC(m, setup.n_chains, w.beta, setup.delta, kmax=kmax, nmax_ops=512, seed=setup.seed,
-                n_tau=n_tau, meas_every=meas_every)
+                n_tau=n_tau, meas_every=meas_every, rebuild_every=rebuild_every)
     if empty_start:
-        chains = [MC.Chain(o, setup.delta, w.beta, [[]] * F, [[]] * F, kmax) for _ in range(setup.n_chains)]
+        starts = [([[]] * F, [[]] * F) for _ in range(setup.n_chains)]
     else:
-        chains = _oracle_chains(setup, o, F, kmax)
-    mc.set_configs([(ch.cre, ch.ann) for ch in chains])
+        starts = list(I.mc_initial_configs(setup))
+    reps = OP.replay_chains(w.params, w.retain_window, setup.delta, w.beta, kmax, starts, setup.seed, n_moves,
+                            n_tau, meas_every)
+    mc.set_configs([(r["start"][0], r["start"][1]) for r in reps])
     st0 = mc.state()
-    for c, ch in enumerate(chains):
-        assert st0["sign"][c] == ch.sign and st0["logw"][c] == pytest.approx(ch.logw, abs=1e-10)
+    for c, r in enumerate(reps):
+        assert st0["sign"][c] == r["start"][2] and st0["logw"][c] == pytest.approx(r["start"][3], abs=1e-10)
     mc.sweep(n_moves)
-    acc = np.zeros((setup.n_chains, F, n_tau))
-    margins, accepted = [], 0
-    for step in range(n_moves):
-        for c, ch in enumerate(chains):
-            kind, a = ch.step(MC.move_uniforms(setup.seed, c, step))
-            accepted += a
-            if kind:
-                margins.append(ch.last_margin)
-            if (step + 1) % meas_every == 0:
-                ch.measure(acc[c])
-    assert min(margins) > 1e-8, "a decision within rounding of its threshold: replay not comparable"
+    assert min(r["min_margin"] for r in reps) > 1e-8, \
+        "a decision within rounding of its threshold: replay not comparable"
+    accepted = sum(r["accepted"] for r in reps)
+    acc = np.stack([r["acc"] for r in reps])
     st = mc.state(with_M=True)
     worst_M = worst_w = 0.0
-    for c, ch in enumerate(chains):
+    for c, r in enumerate(reps):
         for f in range(F):
-            k = len(ch.cre[f])
+            k = len(r["cre"][f])
             assert st["k"][c, f] == k, (c, f)
-            assert list(st["cre"][c, f, :k]) == ch.cre[f] and list(st["ann"][c, f, :k]) == ch.ann[f], (c, f)
+            assert list(st["cre"][c, f, :k]) == r["cre"][f] and list(st["ann"][c, f, :k]) == r["ann"][f], (c, f)
             if k:
-                Mi = np.linalg.inv(MC.hyb_matrix(setup.delta, w.beta, ch.cre[f], ch.ann[f]))
+                Mi = np.linalg.inv(MC.hyb_matrix(setup.delta, w.beta, r["cre"][f], r["ann"][f]))
                 worst_M = max(worst_M, np.max(np.abs(st["M"][c, f, :k, :k] - Mi)) / np.max(np.abs(Mi)))
-        assert st["sign"][c] == ch.sign, c
-        worst_w = max(worst_w, abs(st["logw"][c] - ch.logw))
+        assert st["sign"][c] == r["sign"], c
+        worst_w = max(worst_w, abs(st["logw"][c] - r["logw"]))
     assert worst_M <= 1e-10 and worst_w <= 1e-10, (worst_M, worst_w)
     g, ms, nm = mc.accumulators()
     assert np.all(nm == n_moves // meas_every)
@@ -99,7 +97,8 @@ def _replay_and_compare(which, n_chains, n_moves, kmax=None, n_tau=20, meas_ever
     stats = mc.stats()
     assert stats["moves"] == n_moves * setup.n_chains
     assert stats["insert_accepted"] + stats["remove_accepted"] == accepted
-    print(f"accepted {accepted} of {n_moves * setup.n_chains}; M {worst_M:.1e}, logw {worst_w:.1e}")
+    print(f"accepted {accepted} of {n_moves * setup.n_chains}; M {worst_M:.1e}, logw {worst_w:.1e}, "
+          f"largest drift found at a rebuild {stats['max_drift']:.1e}")
     mc.close()
     return accepted
 
@@ -108,10 +107,15 @@ def test_mc_two_orbital_trajectory_matches_oracle():
     assert _replay_and_compare(6, 8, 150) > 50
 
 
+def test_mc_two_orbital_trajectory_with_rebuilds():
+    """M rebuilt from scratch every 25 moves: the same chains as the oracle's."""
+    assert _replay_and_compare(6, 8, 150, rebuild_every=25) > 50
+
+
 def test_mc_five_orbital_trajectory_matches_oracle():
     """High initial orders (up to 200 pairs over 10 flavors): large M updates and
-    long operator lists in every trace."""
-    assert _replay_and_compare(3, 4, 12) >= 1
+    long operator lists in every trace; 16 chains over 40 moves."""
+    assert _replay_and_compare(3, 16, 40) >= 20
 
 
 def test_mc_capacity_limits_match_oracle():
@@ -250,3 +254,90 @@ def test_mc_graph_replays_match_direct_launches():
           f"{st['insert_accepted'] + st['remove_accepted']}")
     direct.close()
     graph.close()
+
+
+def test_mc_long_run_inverse_stays_exact():
+    """5,100 moves of 256 two-orbital chains with M rebuilt every 1,000 moves: M is
+    then 100 fast updates away from its last rebuild and must equal inv(A) of the
+    chain's times to 1e-8; the drift found at the rebuilds is reported."""
+    _require_gpu()
+    setup = I.mc_setup(6, 256)
+    w = setup.workload
+    m = hyb.model_for_workload(w)
+    o = T.build(w.params, w.retain_window)
+    F = 2 * w.params.n_orb
+    start = [(ch.cre, ch.ann) for ch in _oracle_chains(setup, o, F, setup.kmax_flavor)]
+    out = {}
+    for every in (1000, 0):
+        mc = hyb.MC(m, setup.n_chains, w.beta, setup.delta, kmax=setup.kmax_flavor, nmax_ops=512,
+                    seed=setup.seed, n_tau=10, meas_every=10, moves_per_sweep=100, rebuild_every=every)
+        mc.set_configs(start)
+        mc.sweep(51)
+        st = mc.state(with_M=True)
+        worst, kmax_seen = 0.0, 0
+        for c in range(setup.n_chains):
+            for f in range(F):
+                k = int(st["k"][c, f])
+                kmax_seen = max(kmax_seen, k)
+                if k:
+                    Mi = np.linalg.inv(MC.hyb_matrix(setup.delta, w.beta, st["cre"][c, f, :k], st["ann"][c, f, :k]))
+                    worst = max(worst, np.max(np.abs(st["M"][c, f, :k, :k] - Mi)) / np.max(np.abs(Mi)))
+        stats = mc.stats()
+        out[every] = (worst, stats["max_drift"])
+        print(f"rebuild_every={every}: {mc.step_count()} moves, largest k {kmax_seen}, "
+              f"M against inv(A) {worst:.2e}, drift found at rebuilds {stats['max_drift']:.2e}")
+        assert mc.step_count() == 5100
+        mc.close()
+    assert out[1000][0] <= 1e-8
+    assert out[1000][1] <= 1e-8
+
+
+def test_mc_checkpoint_resume_bitwise():
+    """Save after 70 moves, load into a fresh chain set, continue: bitwise the same
+    chains, accumulators and statistics as the uninterrupted run (rebuilds of M on
+    the way, and graph replays after the load).  A checkpoint of other chains or with
+    a corrupted stored trace is refused."""
+    _require_gpu()
+    setup = I.mc_setup(6, 32)
+    w = setup.workload
+    m = hyb.model_for_workload(w)
+    o = T.build(w.params, w.retain_window)
+    F = 2 * w.params.n_orb
+    mk = lambda seed=setup.seed: hyb.MC(m, setup.n_chains, w.beta, setup.delta, kmax=setup.kmax_flavor,
+                                        nmax_ops=512, seed=seed, n_tau=10, meas_every=2, rebuild_every=50)
+    a = mk()
+    a.set_configs([(ch.cre, ch.ann) for ch in _oracle_chains(setup, o, F, setup.kmax_flavor)])
+    a.sweep(70)
+    blob = a.save()
+    a.sweep(60)
+    b = mk()
+    b.load(blob)
+    assert b.step_count() == 70
+    b.set_graphs(True)
+    b.sweep(60)
+    _same_chains(a, b)
+    st = a.stats()
+    print(f"checkpoint of {len(blob)} bytes; after 130 moves accepted "
+          f"{st['insert_accepted'] + st['remove_accepted']}, drift at rebuilds {st['max_drift']:.1e}")
+    # refused: other seed, truncated blob, a stored trace that does not match its operators
+    other = mk(seed=setup.seed + 1)
+    with pytest.raises(hyb.HybError) as e:
+        other.load(blob)
+    assert e.value.code == -1
+    with pytest.raises(hyb.HybError) as e:
+        b.load(blob[: len(blob) // 2])
+    assert e.value.code == -1
+    C, KM, NM = setup.n_chains, setup.kmax_flavor, 512
+    off = 88 + C * F * 4 + 2 * C * F * KM * 8 + C * F * KM * KM * 8 + C * 4 + C * NM * 8 + C * NM * 2 + C * NM
+    bad = bytearray(blob)
+    logtr0 = np.frombuffer(bytes(bad[off:off + 8]), np.float64)[0]
+    bad[off:off + 8] = np.float64(logtr0 + 1.0).tobytes()
+    with pytest.raises(hyb.HybError) as e:
+        b.load(bytes(bad))
+    assert e.value.code == -1
+    # a refused load leaves the chains usable after a good one
+    b.load(blob)
+    b.sweep(60)
+    _same_chains(a, b)
+    for x in (a, b, other):
+        x.close()

@@ -2,9 +2,11 @@
 
 Forward and backward are compared with the oracle's FP64 network, which rounds to
 BF16 at the same points as the device.  The remaining differences come from FP32
-accumulation and the rare BF16 rounding decisions it flips, so the bars are:
-- logits: 5e-3 relative in norm;
-- gradients: 2e-2 relative in norm per tensor.
+accumulation and the rare BF16 rounding decisions it flips.  Every element is
+checked, against the largest magnitude of its tensor:
+- logits: max |z - z_ref| <= 5e-3 max |z_ref|;
+- gradients: max |g - g_ref| <= 1e-2 max |g_ref| per tensor (the stated BF16/FP32
+  tolerance against FP64).
 Harvested training samples are exact (integer features, bins).  Learned moves replay
 the oracle's chain move by move (configurations exact, divergence allowed only where a
 BF16-level change of the logits can flip a bin draw or an acceptance, which then resyncs
@@ -62,7 +64,8 @@ def _features_batch(n, seed):
 
 
 def _rel(a, b):
-    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
+    """Largest element error against the largest element of the reference."""
+    return float(np.max(np.abs(np.asarray(a, np.float64) - b)) / np.max(np.abs(b)))
 
 
 def test_mlp_forward_matches_oracle():
@@ -98,7 +101,7 @@ def test_mlp_gradients_match_oracle():
     for L in range(3):
         ew, eb = _rel(gW[L], rW[L]), _rel(gb[L], rb[L])
         print(f"layer {L + 1}: dW {ew:.2e}, db {eb:.2e}")
-        assert ew <= 2e-2 and eb <= 2e-2
+        assert ew <= 1e-2 and eb <= 1e-2
     net.close()
 
 
