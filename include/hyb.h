@@ -190,6 +190,25 @@ typedef struct {
 int hyb_trace_batch(hyb_model* m, const hyb_config_batch* cfg, double beta,
                     hyb_trace_out* out, void* stream);
 
+/* hyb_trace_batch for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc).  Same
+ * kernels and results as hyb_trace_batch (bitwise), launched with grids sized for
+ * every (configuration, retained state) pair so that no host round trip sits
+ * between the scan and the path kernels.  The workspace is a static device array
+ * of 64 MiB per GPU (held from the model upload until the process ends); it holds
+ * about 5,000 five-orbital FP64 or 800 seven-orbital mixed-precision
+ * configurations.  No hipMalloc, hipFree or other allocation happens in the call.
+ *  - cfg and out must be device pointers (on_device = 1 in both), else HYB_E_ARG.
+ *  - A batch whose workspace exceeds the static array is refused with HYB_E_ARG
+ *    (the message gives the bytes needed and the maximum).
+ *  - Every call on one GPU uses that GPU's single array: calls that overlap on one
+ *    GPU (several host threads or streams) race and must be serialised by the
+ *    caller.  Counters are cleared by a kernel at the start of each call.
+ *  - Returns after `stream` has drained (it reads the error flags); errors as
+ *    hyb_trace_batch. */
+int hyb_trace_batch_noalloc(hyb_model* m, const hyb_config_batch* cfg, double beta,
+                            hyb_trace_out* out, void* stream);
+
 /* Kernel tuning: which trace-kernel variant hyb_trace_batch launches.
  * variant < 0 restores the automatic choice. Returns HYB_E_ARG for an unknown id. */
 int hyb_set_trace_variant(hyb_model* m, int32_t variant);

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "hyb_internal.h"
@@ -403,6 +404,38 @@ int trace_resident(hyb_model* m, int nc, const int64_t* begin, const int64_t* en
   return 0;
 }
 
+// ---------------------------------------------------------------------------
+// allocation-free entry point: the workspace is a file-scope device array
+// ---------------------------------------------------------------------------
+
+constexpr size_t kScratchBytes = size_t(64) << 20;
+constexpr int kMaxDevices = 64;
+// Workspace of hyb_trace_batch_noalloc.  Host code never uses this name as an
+// address: each device's copy is reached through the pointer hipGetSymbolAddress
+// returned for it (scratch_ptr).
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+static void* scratch_ptr[kMaxDevices] = {};
+static std::mutex scratch_mu;
+
+// Looks up the current device's copy of `scratch` once per device (the model
+// upload calls it with the model's device current).
+static int scratch_init(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return set_error(HYB_E_STATE, "device %d beyond the scratch table", dev);
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (scratch_ptr[dev]) return 0;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p)
+    return set_error(HYB_E_HIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+  scratch_ptr[dev] = p;
+  return 0;
+}
+
+static void* scratch_of(int dev) {
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  return (dev >= 0 && dev < kMaxDevices) ? scratch_ptr[dev] : nullptr;
+}
+
 int trace_resident_variant(const hyb_model* m) { return m->variant >= 0 ? m->variant : auto_variant(m); }
 
 }  // namespace hyb
@@ -508,6 +541,7 @@ int hyb_model_upload(hyb_model* m, void* stream) {
   // host staging vectors above are pageable: make sure the copies finished
   HIP_TRY(hipStreamSynchronize(s));
   for (void*& e : m->events) HIP_TRY(hipEventCreate(reinterpret_cast<hipEvent_t*>(&e)));
+  if ((rc = scratch_init(d.device))) return rc;
   if (m->variant < 0 && auto_variant(m) < 0)
     return set_error(HYB_E_ARG, "no trace kernel variant holds blocks of dimension %d", m->max_dim);
   return HYB_OK;
@@ -804,6 +838,52 @@ int hyb_trace_batch(hyb_model* m, const hyb_config_batch* cfg, double beta, hyb_
     m->last_ms[5] = op;
     m->last_ms[6] = float(nop);
   }
+  return error_from_bits(flags);
+}
+
+int hyb_trace_batch_noalloc(hyb_model* m, const hyb_config_batch* cfg, double beta, hyb_trace_out* out,
+                            void* stream) {
+  if (!m || !cfg || !out) return set_error(HYB_E_ARG, "NULL argument");
+  if (!m->uploaded) return set_error(HYB_E_STATE, "model not uploaded to a device");
+  if (!(beta > 0.0) || !std::isfinite(beta)) return set_error(HYB_E_ARG, "beta must be positive and finite");
+  if (cfg->n_configs < 0) return set_error(HYB_E_ARG, "negative n_configs");
+  if (cfg->n_configs == 0) return HYB_OK;
+  if (!cfg->on_device || !out->on_device)
+    return set_error(HYB_E_ARG, "hyb_trace_batch_noalloc takes device inputs and outputs only");
+  if (!cfg->offsets || !cfg->tau || !cfg->flavor || !cfg->dagger || !out->log_abs || !out->sign)
+    return set_error(HYB_E_ARG, "NULL array");
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev != m->dev.device) return set_error(HYB_E_STATE, "model lives on device %d, current is %d", m->dev.device, dev);
+  void* ws = scratch_of(dev);
+  if (!ws) return set_error(HYB_E_STATE, "scratch of device %d not initialised (upload the model first)", dev);
+  const int vi = m->variant >= 0 ? m->variant : auto_variant(m);
+  const Variant& V = kVariants[vi];
+  const int nc = cfg->n_configs;
+  const int64_t npairs = int64_t(nc) * int64_t(m->ret_block.size());
+  if (npairs > (int64_t(1) << 31) - 1) return set_error(HYB_E_ARG, "too many (config, state) pairs");
+  const size_t vbytes = V.fp64 ? sizeof(double) : sizeof(float);
+  const size_t need = resident_layout(m, nc, vbytes).total;
+  if (need > kScratchBytes) {
+    const size_t per = resident_layout(m, 1, vbytes).total;
+    return set_error(HYB_E_ARG, "%d configurations need %zu bytes of scratch; the maximum is %zu (about %zu "
+                     "configurations of this model)", nc, need, kScratchBytes, kScratchBytes / std::max<size_t>(per, 1));
+  }
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  TraceParams P = resident_params(m, nc, ws, vbytes);
+  P.beta = beta;
+  P.offsets = cfg->offsets;
+  P.ends = nullptr;
+  P.tau = cfg->tau;
+  P.flavor = cfg->flavor;
+  P.dagger = cfg->dagger;
+  // every path stops at its own last operator
+  const int rc = resident_launch(V, P, 1 << 30, out->log_abs, out->sign, out->krylov_steps, out->substeps,
+                                 out->feasible_paths, out->rowsteps, out->rows, s);
+  if (rc) return rc;
+  int32_t flags = 0;
+  HIP_TRY(hipMemcpyAsync(&flags, P.counters + 2, sizeof flags, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
   return error_from_bits(flags);
 }
 

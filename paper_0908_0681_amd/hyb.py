@@ -84,6 +84,7 @@ _SIGS = {
     "hyb_apply_op_device": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, _P, _P, _P, _P]),
     "hyb_propagate_device": (C.c_int, [_P, C.c_int32, C.c_int32, _P, _P, _P, _P, _P, _P]),
     "hyb_trace_batch": (C.c_int, [_P, C.POINTER(ConfigBatchC), C.c_double, C.POINTER(TraceOutC), _P]),
+    "hyb_trace_batch_noalloc": (C.c_int, [_P, C.POINTER(ConfigBatchC), C.c_double, C.POINTER(TraceOutC), _P]),
     "hyb_set_trace_variant": (C.c_int, [_P, C.c_int32]),
     "hyb_get_trace_variant": (C.c_int, [_P, _P]),
     "hyb_trace_variant_count": (C.c_int, [_P]),
@@ -341,6 +342,12 @@ class Model:
         """dev_batch / out: dicts of torch device tensors (see bench.py)."""
         cfg, o = self._device_args(dev_batch, out)
         _check(lib().hyb_trace_batch(self.h, C.byref(cfg), beta, C.byref(o), _stream(stream)))
+
+    def trace_batch_noalloc(self, dev_batch, beta, out, stream=None):
+        """hyb_trace_batch_noalloc: as trace_batch_device, with the library's static
+        device workspace instead of an allocated one."""
+        cfg, o = self._device_args(dev_batch, out)
+        _check(lib().hyb_trace_batch_noalloc(self.h, C.byref(cfg), beta, C.byref(o), _stream(stream)))
 
     def block_spmm(self, b, X, Y, n_vec, stream=None):
         _check(lib().hyb_block_spmm(self.h, b, n_vec, _ptr(X), _ptr(Y), _stream(stream)))
