@@ -183,6 +183,68 @@ def measure_mc(torch, hyb, I, moves=40, warm=10, which=3, n_chains=None, graphs=
     return res
 
 
+def measure_comparator(torch, hyb, I, orbitals=(2, 3, 4, 5, 6, 7), n_configs=512, reps=3):
+    """The Krylov path against the matrix formulation (Sec. IV.B): for n = 2..7
+    orbitals at U = 6, J = U/6, beta = 50, the same batch of configurations through
+    hyb_trace_batch (FP64 Krylov, tolerance 1e-13) and hyb_trace_batch_matrix (FP64
+    eigenbasis products); device-resident inputs, median of reps timed calls each.
+    The matrix path's roofline: the operator-block bytes it reads (8 d_t d_b per
+    operator of every feasible path) over its time, against the HBM peak."""
+    import numpy as np
+    rows = []
+    for n in orbitals:
+        w = I.comparator_workload(n, n_configs)
+        m = hyb.model_for_workload(w)
+        b = w.batch()
+        db = device_batch(b, torch)
+        outk, outm = device_out(b.n_configs, torch), device_out(b.n_configs, torch)
+        t0 = time.perf_counter()
+        m.matrix_build()
+        build_s = time.perf_counter() - t0
+        info = m.matrix_info()
+
+        def timed(fn, out):
+            fn(db, b.beta, out)
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(reps):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                fn(db, b.beta, out)
+                e1.record()
+                torch.cuda.synchronize()
+                ts.append(e0.elapsed_time(e1))
+            return sorted(ts)[len(ts) // 2]
+
+        ms_k = timed(m.trace_batch_device, outk)
+        ms_m = timed(m.trace_batch_matrix_device, outm)
+        sk, sm = outk["sign"].cpu().numpy(), outm["sign"].cpu().numpy()
+        lk, lm = outk["log_abs"].cpu().numpy(), outm["log_abs"].cpu().numpy()
+        # configurations where the two formulations agree to 1e-6 (signs and zeros
+        # exact); the rest are counted: the FP64 eigenbasis route mixes nearly
+        # degenerate levels of different symmetry, which long intervals amplify
+        both = (sk == sm) & (sk != 0)
+        rel = np.abs(np.expm1(lk[both] - lm[both]))
+        agree = int(np.sum(rel <= 1e-6)) + int(np.sum((sk == 0) & (sm == 0)))
+        rel_ok = rel[rel <= 1e-6]
+        mat_bytes = 8.0 * float(outm["rowsteps"].sum().item())
+        print(f"[comparator] n={n}: Krylov {ms_k:.3f} ms, matrix {ms_m:.3f} ms", file=sys.stderr, flush=True)
+        rows.append({"workload": w.name, "n_orb": n, "max_block": m.info()["max_dim"],
+                     "n_retained": m.info()["n_retained"], "ops_per_config": float(np.diff(b.offsets).mean()),
+                     "n_configs": b.n_configs, "krylov_traces_per_s": b.n_configs / (ms_k / 1e3),
+                     "matrix_traces_per_s": b.n_configs / (ms_m / 1e3),
+                     "krylov_over_matrix": ms_m / ms_k, "krylov_ms": ms_k, "matrix_ms": ms_m,
+                     "agree_1e-6": agree, "apart": int(b.n_configs - agree),
+                     "agree_max_rel_diff": float(rel_ok.max()) if rel_ok.size else 0.0,
+                     "agree_median_rel_diff": float(np.median(rel_ok)) if rel_ok.size else 0.0,
+                     "matrix_op_bytes": info["op_bytes"], "matrix_build_s": build_s,
+                     "matrix_GBps": mat_bytes / (ms_m / 1e3) / 1e9,
+                     "matrix_hbm_frac": mat_bytes / (ms_m / 1e3) / 1e9 / HBM_PEAK_GBS})
+        del m
+        torch.cuda.empty_cache()
+    return rows
+
+
 def measure_spmm(torch, hyb, I, n_vec=262144, reps=10):
     """Gated bandwidth benchmark: Y = (H_b - c_b) X on the 7-orbital (n_up, n_dn) =
     (3, 4) block (1225 states, 8400 off-diagonal entries), FP32, 16-vector panels.
@@ -494,6 +556,8 @@ def main():
     ap.add_argument("--ess-seed", type=int, default=0, help="offset of the chains' seeds")
     ap.add_argument("--ess-eps", type=float, default=0.1, help="uniform share of the learned insertion density")
     ap.add_argument("--no-seven", action="store_true", help="skip the 7-orbital mixed workload")
+    ap.add_argument("--no-comparator", action="store_true", help="skip the Krylov vs matrix comparison")
+    ap.add_argument("--comparator-only", action="store_true", help="only the Krylov vs matrix comparison")
     ap.add_argument("--seven-only", action="store_true", help="only the 7-orbital mixed workload (profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (3 times) and exit: the reference "
@@ -525,6 +589,9 @@ def main():
         return
     if a.ess_only:
         print(json.dumps({"ess": measure_ess(torch, hyb, I, moves=a.ess_moves, eps=a.ess_eps, seed_offset=a.ess_seed)}), flush=True)
+        return
+    if a.comparator_only:
+        print(json.dumps({"matrix_vs_krylov": measure_comparator(torch, hyb, I)}), flush=True)
         return
     if a.seven_only:
         r7 = measure_workload(2, a.steps, a.warmup, torch, hyb, I)
@@ -577,6 +644,8 @@ def main():
                                        moves_per_sweep=100)}
     if not a.no_spmm:
         line["detail"]["spmm_gated"] = measure_spmm(torch, hyb, I)
+    if not a.no_comparator:
+        line["detail"]["matrix_vs_krylov"] = measure_comparator(torch, hyb, I)
     if not a.no_ess:
         line["detail"]["ess"] = measure_ess(torch, hyb, I, moves=a.ess_moves, eps=a.ess_eps, seed_offset=a.ess_seed)
     if not a.no_cpu:

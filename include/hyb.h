@@ -53,7 +53,10 @@ extern "C" {
 #define HYB_E_STATE      -8  /* handle used in a state that does not allow the call */
 
 /* ---- model --------------------------------------------------------------- */
-#define HYB_CSR          0   /* H_loc blocks stored as CSR */
+#define HYB_CSR          0   /* H_loc blocks stored as CSR (and padded ELL copies) on the device */
+#define HYB_MATRIX_FREE  1   /* no off-diagonal matrix on the device: the trace kernels generate the
+                                spin-flip and pair-hopping entries of Eq.(4) of each row from its bit
+                                pattern at every SpMV (hyb_block_spmm needs HYB_CSR) */
 #define HYB_FP64         0   /* Krylov vectors, SpMV and recurrences in float64 */
 #define HYB_MIXED        1   /* float32 Krylov vectors and off-diagonal SpMV with float32
                                 accumulation; float64 diagonal, Lanczos alpha/beta,
@@ -68,7 +71,7 @@ typedef struct {
   double J;               /* Hund coupling in the density-density part (Up - J) */
   double J_sf;            /* spin-flip amplitude (J in Eq.(4); 0 gives a density-density model) */
   double J_ph;            /* pair-hopping amplitude (J in Eq.(4)) */
-  int32_t storage;        /* HYB_CSR */
+  int32_t storage;        /* HYB_CSR or HYB_MATRIX_FREE */
   int32_t precision;      /* HYB_FP64 or HYB_MIXED */
   double retain_window;   /* retained set R = {E_i - E0 <= retain_window}; < 0: all states
                              (full trace).  Sec. III step 2, Sec. IV.C (energy window) */
@@ -233,6 +236,33 @@ int hyb_get_chunk(const hyb_model* m, int32_t* chunk);
  * Requires hyb_set_timing(m, 1) before the call. */
 int hyb_set_timing(hyb_model* m, int32_t on);
 int hyb_last_timing(const hyb_model* m, float* out7);
+
+/* ---- the matrix formulation (the comparison path) ----------------------------- */
+
+/* Builds the matrix formulation of Sec. II (Eq.(3)) on the model's device: every
+ * block's full eigendecomposition (host, FP64, threads over blocks) and, for every
+ * block b and operator c_f / c_f^dag with a physical target block t, the dense FP64
+ * block U_t^T O U_b in the two eigenbases (one rocBLAS DGEMM per block on the
+ * device).  Device memory: the sum of d_t d_b over those blocks, 8 bytes each
+ * (2.3 GB at 7 orbitals); host time: the eigendecompositions.  Replaces an
+ * earlier build; freed with the model.  Errors: HYB_E_STATE (model not uploaded),
+ * HYB_E_OOM, HYB_E_HIP. */
+int hyb_matrix_build(hyb_model* m, void* stream);
+
+/* Device bytes of the operator blocks and the seconds the build took. */
+int hyb_matrix_info(const hyb_model* m, int64_t* op_bytes, double* build_seconds);
+
+/* Tr_R of every configuration by the matrix formulation: one workgroup per feasible
+ * (configuration, retained state) path, each interval a diagonal scaling by
+ * exp(-dtau (E_b - E0)) in the eigenbasis, each operator a dense product with its
+ * eigenbasis block, renormalisation with a running log-norm, and the signed
+ * log-sum over R.  Same arguments, outputs, zero rule (squared norm below 1e-20 of
+ * a unit vector) and errors as hyb_trace_batch; krylov_steps and substeps are 0,
+ * rowsteps counts the operator-block elements read and rows the target
+ * dimensions.  FP64 whatever the model's precision.  HYB_E_STATE before
+ * hyb_matrix_build or after a new hyb_model_upload. */
+int hyb_trace_batch_matrix(hyb_model* m, const hyb_config_batch* cfg, double beta, hyb_trace_out* out,
+                           void* stream);
 
 /* ---- block SpMM over many vectors ------------------------------------------ */
 

@@ -45,9 +45,9 @@ def _spawn_pool(workers, initializer, initargs):
 # traces
 # ---------------------------------------------------------------------------
 
-def _trace_init(params, window, zero_tol, batch):
+def _trace_init(params, window, zero_tol, batch, method):
     from . import trace as T
-    _W["oracle"] = T.build(params, window, zero_tol=zero_tol)
+    _W["oracle"] = T.build(params, window, zero_tol=zero_tol, method=method)
     _W["batch"] = batch
 
 
@@ -57,8 +57,8 @@ def _trace_chunk(idx):
     return idx, r, time.perf_counter() - t0
 
 
-def trace_batch(params, window, batch, configs=None, zero_tol=1e-10, workers=None, chunk=1):
-    """oracle.trace.build(params, window, zero_tol).trace_batch(batch, configs),
+def trace_batch(params, window, batch, configs=None, zero_tol=1e-10, workers=None, chunk=1, method="auto"):
+    """oracle.trace.build(params, window, zero_tol, method).trace_batch(batch, configs),
     evaluated by a process pool.  Returns (TraceResult, info) where info holds the
     worker count and the seconds spent in trace evaluation (model setup excluded)."""
     from .trace import TraceResult
@@ -66,7 +66,7 @@ def trace_batch(params, window, batch, configs=None, zero_tol=1e-10, workers=Non
     workers = workers or default_workers()
     workers = max(1, min(workers, len(idx)))
     chunks = [idx[i:i + chunk] for i in range(0, len(idx), chunk)]
-    with _spawn_pool(workers, _trace_init, (params, window, zero_tol, batch)) as pool:
+    with _spawn_pool(workers, _trace_init, (params, window, zero_tol, batch, method)) as pool:
         # the first round of tasks is timed from the moment every worker holds its oracle
         pool.map(_noop, range(workers), chunksize=1)
         t0 = time.perf_counter()

@@ -6,7 +6,9 @@ records the fastest in a JSON cache keyed by (gpu arch, n_orb, precision).
 hyb.model_for_workload applies the cached choice; without a cache the
 library's own heuristic is used.
 
-Usage (on a GPU): python -m paper_0908_0681_amd.autotune [--workloads 1 2] [--reps 3]
+Usage (on a GPU): python -m paper_0908_0681_amd.autotune [--workloads 1 2] [--comparator 2 3 4 6 7] [--reps 3]
+(--comparator tunes the FP64 models of the Krylov-against-matrix comparison at the
+given orbital counts.)
 """
 from __future__ import annotations
 
@@ -36,11 +38,11 @@ def gpu_arch() -> str:
     return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
 
 
-def tune(k: int, reps: int = 3, n_configs: int | None = None) -> dict:
+def tune(w, reps: int = 3, n_configs: int | None = None) -> dict:
+    """Times every fitting variant, then the launch schedules of the fastest, on
+    workload w (an inputs.Workload)."""
     import torch
     from . import hyb
-    from . import inputs as I
-    w = I.workload(k)
     model = hyb.model_for_workload(w, use_cache=False)
     batch = w.batch(n_configs)
     dev = {key: torch.tensor(getattr(batch, key), device="cuda") for key in ("offsets", "tau", "flavor", "dagger")}
@@ -78,16 +80,16 @@ def tune(k: int, reps: int = 3, n_configs: int | None = None) -> dict:
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workloads", type=int, nargs="+", default=[1, 2])
+    ap.add_argument("--workloads", type=int, nargs="*", default=[1, 2])
+    ap.add_argument("--comparator", type=int, nargs="*", default=[])
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--out", default=CACHE)
     a = ap.parse_args()
     from . import inputs as I
     cache = load_cache()
     arch = gpu_arch()
-    for k in a.workloads:
-        r = tune(k, a.reps)
-        w = I.workload(k)
+    for w in [I.workload(k) for k in a.workloads] + [I.comparator_workload(n) for n in a.comparator]:
+        r = tune(w, a.reps)
         cache[cache_key(arch, w.params.n_orb, w.precision)] = {
             "variant": r["best"], "ms": r["ms"], "chunk": r["chunk"], "chunk_ms": r["chunk_ms"]}
         print(json.dumps(r), flush=True)

@@ -17,12 +17,16 @@ struct BlockDev {
   int32_t state_off;  // offset of the block's states in the packed state / row arrays
   int32_t n_up, n_dn;
   double shift;       // c_b: lowest eigenvalue of the block; kernels apply H_b - c_b
+  int32_t up_states;  // C(n_orb, n_up): index of state (up, dn) = rank_half[dn] * up_states + rank_half[up]
+  int32_t pad_;
 };
 
 struct DeviceModel {
   // basis
   uint32_t* states = nullptr;   // [n_states] packed by block, ascending inside a block
   int32_t* rank = nullptr;      // [n_states] state integer -> index inside its block
+  int16_t* rank_half = nullptr; // [2^n_orb] one spin's occupation pattern -> its rank among the
+                                // patterns of the same popcount (ascending integers)
   BlockDev* blocks = nullptr;   // [n_blocks]
   // off-diagonal CSR over the packed rows (column = index inside the same block)
   int32_t* rowptr = nullptr;    // [n_states + 1]
@@ -65,6 +69,7 @@ struct hyb_model {
   // basis
   std::vector<uint32_t> states;      // packed by block
   std::vector<int32_t> rank;         // state -> index inside block
+  std::vector<int16_t> rank_half;    // one spin's pattern -> rank among same-popcount patterns
   std::vector<int32_t> block_of;     // state -> block
   std::vector<hyb::BlockDev> blocks;
   // H_loc: diagonal + off-diagonal CSR (packed rows)
@@ -76,6 +81,7 @@ struct hyb_model {
   double E0 = 0.0;
   // retained set
   std::vector<int32_t> ret_block;
+  std::vector<int32_t> ret_index;    // eigen-index of each retained state inside its block
   std::vector<double> ret_energy;
   std::vector<int64_t> ret_off;
   std::vector<double> ret_vec;
@@ -93,6 +99,7 @@ struct hyb_model {
   float last_ms[7] = {0, 0, 0, 0, 0, 0, 0};
   void* events[4] = {nullptr, nullptr, nullptr, nullptr};
   std::vector<void*> step_events;  // pairs around each step launch when timing
+  void* mat = nullptr;      // matrix formulation (matrix.hip), built by hyb_matrix_build
 };
 
 namespace hyb {
@@ -102,4 +109,5 @@ namespace hyb {
 // vec, row-major n x n_vec).  Returns 0 or a negative error code.
 int sym_eig(int n, const double* a, double* evals, int n_vec, double* vec);
 void free_device(hyb_model* m);
+void matrix_release(hyb_model* m);  // matrix.hip: frees the matrix formulation's device data
 }  // namespace hyb

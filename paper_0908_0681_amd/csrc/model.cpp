@@ -102,6 +102,12 @@ int build_basis(hyb_model& m) {
   m.states.assign(m.n_states, 0);
   for (int64_t s = 0; s < m.n_states; ++s)
     m.states[m.blocks[m.block_of[s]].state_off + m.rank[s]] = uint32_t(s);
+  // one spin's patterns ranked among those of equal popcount; blocks list states by
+  // ascending integer up | dn << n, so a state's index is rank(dn) * C(n, n_up) + rank(up)
+  m.rank_half.assign(size_t(1) << n, 0);
+  std::vector<int16_t> seen(n + 1, 0);
+  for (uint32_t x = 0; x < (1u << n); ++x) m.rank_half[x] = seen[popc(x)]++;
+  for (int b = 0; b < m.n_blocks; ++b) m.blocks[b].up_states = seen[m.blocks[b].n_up];
   return 0;
 }
 
@@ -219,6 +225,7 @@ int build_spectrum(hyb_model& m) {
     m.blocks[b].shift = m.evals[b][0];
   }
   m.ret_block.clear();
+  m.ret_index.clear();
   m.ret_energy.clear();
   m.ret_off.clear();
   m.ret_vec.clear();
@@ -227,6 +234,7 @@ int build_spectrum(hyb_model& m) {
     for (int j = 0; j < nvec[b]; ++j) {
       if (w >= 0.0 && m.evals[b][j] - m.E0 > w) break;
       m.ret_block.push_back(b);
+      m.ret_index.push_back(j);
       m.ret_energy.push_back(m.evals[b][j]);
       m.ret_off.push_back(int64_t(m.ret_vec.size()));
       for (int i = 0; i < d; ++i) m.ret_vec.push_back(vecs[b][size_t(i) * nvec[b] + j]);
@@ -250,7 +258,8 @@ int hyb_model_create(const hyb_model_params* p, hyb_model** out) {
   *out = nullptr;
   if (p->n_orb < 1 || p->n_orb > 7) return set_error(HYB_E_ARG, "n_orb must be in 1..7 (got %d)", p->n_orb);
   if (!p->eps) return set_error(HYB_E_ARG, "eps is NULL");
-  if (p->storage != HYB_CSR) return set_error(HYB_E_ARG, "unsupported storage %d", p->storage);
+  if (p->storage != HYB_CSR && p->storage != HYB_MATRIX_FREE)
+    return set_error(HYB_E_ARG, "unsupported storage %d", p->storage);
   if (p->precision != HYB_FP64 && p->precision != HYB_MIXED)
     return set_error(HYB_E_ARG, "unknown precision %d", p->precision);
   if (p->krylov_max < 2 || p->krylov_max > 20) return set_error(HYB_E_ARG, "krylov_max must be in 2..20");

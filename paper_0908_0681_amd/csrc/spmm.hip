@@ -121,6 +121,7 @@ using namespace hyb;
 extern "C" int hyb_block_spmm(hyb_model* m, int32_t block, int64_t n_vec, const float* X, float* Y, void* stream) {
   if (!m || !X || !Y) return set_error(HYB_E_ARG, "NULL argument");
   if (!m->uploaded) return set_error(HYB_E_STATE, "model not uploaded");
+  if (m->p.storage != HYB_CSR) return set_error(HYB_E_STATE, "the block SpMM reads the ELL copy: needs HYB_CSR storage");
   if (block < 0 || block >= m->n_blocks) return set_error(HYB_E_ARG, "block %d out of range", block);
   if (n_vec < 0 || n_vec % 16) return set_error(HYB_E_ARG, "n_vec must be a non-negative multiple of 16");
   const BlockDev& B = m->blocks[block];

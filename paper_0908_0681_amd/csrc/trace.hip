@@ -48,19 +48,19 @@ __global__ __launch_bounds__(NT) void k_path_op(TraceParams P, int k) {
   path_op<VT, NT, RPT>(P, blockIdx.x, k, red);
 }
 
-template <typename VT, int NT, int RPT, int MAXM>
-__global__ __launch_bounds__(NT) void k_path_prop(TraceParams P, int k) {
-  __shared__ typename PathEngine<VT, NT, RPT, MAXM>::Smem S;
+template <typename VT, int NT, int RPT, int MAXM, bool MF, bool VL, int OCC>
+__global__ __launch_bounds__(NT, OCC) void k_path_prop(TraceParams P, int k) {
+  __shared__ typename PathEngine<VT, NT, RPT, MAXM, MF, VL>::Smem S;
   if (int(blockIdx.x) >= P.counters[0]) return;
-  path_prop<VT, NT, RPT, MAXM>(P, blockIdx.x, k, S);
+  path_prop<VT, NT, RPT, MAXM, MF, VL>(P, blockIdx.x, k, S);
 }
 
 // Operators [k0, k1) of every path, one workgroup per path: the propagation before
 // operator k (k > 0) and the operator itself, exactly as the single-step kernels,
 // separated by workgroup barriers (the path's vector passes through global memory).
-template <typename VT, int NT, int RPT, int MAXM>
-__global__ __launch_bounds__(NT) void k_path_chunk(TraceParams P, int k0, int k1) {
-  __shared__ typename PathEngine<VT, NT, RPT, MAXM>::Smem S;
+template <typename VT, int NT, int RPT, int MAXM, bool MF, bool VL, int OCC>
+__global__ __launch_bounds__(NT, OCC) void k_path_chunk(TraceParams P, int k0, int k1) {
+  __shared__ typename PathEngine<VT, NT, RPT, MAXM, MF, VL>::Smem S;
   __shared__ double red[NT / 64];
   const int w = blockIdx.x;
   if (w >= P.counters[0]) return;
@@ -72,7 +72,7 @@ __global__ __launch_bounds__(NT) void k_path_chunk(TraceParams P, int k0, int k1
   }
   for (int k = k0; k < k1; ++k) {
     if (k > 0) {
-      path_prop<VT, NT, RPT, MAXM>(P, w, k, S);
+      path_prop<VT, NT, RPT, MAXM, MF, VL>(P, w, k, S);
       __syncthreads();
     }
     path_op<VT, NT, RPT>(P, w, k, red);
@@ -110,10 +110,10 @@ __global__ void k_apply_op(const uint32_t* states, const int32_t* rank, BlockDev
 
 // Krylov propagation of a batch of vectors of one block (parity hook): one
 // workgroup per vector, same engine as the trace kernel.
-template <typename VT, int NT, int RPT, int MAXM>
-__global__ __launch_bounds__(NT) void k_propagate(TraceParams P, int block, const VT* x, const double* dtau,
-                                                  VT* y, double* log_scale, int32_t* steps_out) {
-  using E = PathEngine<VT, NT, RPT, MAXM>;
+template <typename VT, int NT, int RPT, int MAXM, bool MF, bool VL, int OCC>
+__global__ __launch_bounds__(NT, OCC) void k_propagate(TraceParams P, int block, const VT* x, const double* dtau,
+                                                       VT* y, double* log_scale, int32_t* steps_out) {
+  using E = PathEngine<VT, NT, RPT, MAXM, MF, VL>;
   __shared__ typename E::Smem S;
   E eng(P, S);
   const BlockDev B = P.blocks[block];
@@ -154,6 +154,7 @@ struct Variant {
   const char* name;
   int fp64;   // 1: float64 vectors, 0: float32 (mixed)
   int nt, rpt, maxm;
+  int mf;     // 1: matrix-free rows (needs no off-diagonal matrix on the device)
   const void* init_fn;   // k_path_init
   const void* op_fn;     // k_path_op
   const void* step_fn;   // k_path_prop
@@ -162,30 +163,45 @@ struct Variant {
   const void* chunk_fn;  // k_path_chunk
 };
 
-#define VARIANT(VT, NT, RPT, MAXM, NAME)                                                      \
-  {NAME, sizeof(VT) == 8, NT, RPT, MAXM, reinterpret_cast<const void*>(&k_path_init<VT, NT>),  \
-   reinterpret_cast<const void*>(&k_path_op<VT, NT, RPT>),                                    \
-   reinterpret_cast<const void*>(&k_path_prop<VT, NT, RPT, MAXM>),                            \
-   reinterpret_cast<const void*>(&k_path_final<VT, NT, RPT>),                                 \
-   reinterpret_cast<const void*>(&k_propagate<VT, NT, RPT, MAXM>),                            \
-   reinterpret_cast<const void*>(&k_path_chunk<VT, NT, RPT, MAXM>)}
+// MF: matrix-free rows; VL: Krylov basis in LDS; OCC: workgroups per CU the compiler
+// must leave register room for
+#define VARIANT(VT, NT, RPT, MAXM, MF, VL, OCC, NAME)                                             \
+  {NAME, sizeof(VT) == 8, NT, RPT, MAXM, MF, reinterpret_cast<const void*>(&k_path_init<VT, NT>),   \
+   reinterpret_cast<const void*>(&k_path_op<VT, NT, RPT>),                                        \
+   reinterpret_cast<const void*>(&k_path_prop<VT, NT, RPT, MAXM, MF, VL, OCC>),                   \
+   reinterpret_cast<const void*>(&k_path_final<VT, NT, RPT>),                                     \
+   reinterpret_cast<const void*>(&k_propagate<VT, NT, RPT, MAXM, MF, VL, OCC>),                   \
+   reinterpret_cast<const void*>(&k_path_chunk<VT, NT, RPT, MAXM, MF, VL, OCC>)}
 
 static const Variant kVariants[] = {
-    VARIANT(double, 64, 1, 12, "f64_nt64_r1_m12"),
-    VARIANT(double, 64, 2, 12, "f64_nt64_r2_m12"),
-    VARIANT(double, 64, 2, 16, "f64_nt64_r2_m16"),
-    VARIANT(double, 128, 1, 12, "f64_nt128_r1_m12"),
-    VARIANT(double, 256, 5, 12, "f64_nt256_r5_m12"),
-    VARIANT(float, 64, 2, 12, "f32_nt64_r2_m12"),
-    VARIANT(float, 256, 5, 12, "f32_nt256_r5_m12"),
-    VARIANT(float, 256, 5, 16, "f32_nt256_r5_m16"),
-    VARIANT(float, 512, 3, 12, "f32_nt512_r3_m12"),
-    VARIANT(float, 512, 3, 16, "f32_nt512_r3_m16"),
+    VARIANT(double, 64, 1, 12, false, false, 1, "f64_nt64_r1_m12"),
+    VARIANT(double, 64, 2, 12, false, false, 1, "f64_nt64_r2_m12"),
+    VARIANT(double, 64, 2, 16, false, false, 1, "f64_nt64_r2_m16"),
+    VARIANT(double, 128, 1, 12, false, false, 1, "f64_nt128_r1_m12"),
+    VARIANT(double, 128, 4, 12, false, false, 1, "f64_nt128_r4_m12"),
+    VARIANT(double, 256, 2, 12, false, false, 1, "f64_nt256_r2_m12"),
+    VARIANT(double, 256, 5, 12, false, false, 1, "f64_nt256_r5_m12"),
+    VARIANT(float, 64, 2, 12, false, false, 1, "f32_nt64_r2_m12"),
+    VARIANT(float, 256, 5, 12, false, false, 1, "f32_nt256_r5_m12"),
+    VARIANT(float, 256, 5, 16, false, false, 1, "f32_nt256_r5_m16"),
+    VARIANT(float, 512, 3, 12, false, false, 1, "f32_nt512_r3_m12"),
+    VARIANT(double, 64, 2, 12, true, false, 1, "f64_nt64_r2_m12_mf"),
+    VARIANT(double, 256, 5, 12, true, false, 1, "f64_nt256_r5_m12_mf"),
+    VARIANT(float, 64, 2, 12, true, false, 1, "f32_nt64_r2_m12_mf"),
+    VARIANT(float, 256, 5, 12, true, false, 1, "f32_nt256_r5_m12_mf"),
+    VARIANT(float, 64, 20, 8, false, true, 1, "f32_nt64_r20_m8_vl"),
+    VARIANT(float, 64, 20, 8, true, true, 1, "f32_nt64_r20_m8_vl_mf"),
+    VARIANT(double, 64, 2, 12, false, true, 1, "f64_nt64_r2_m12_vl"),
 };
 static const int kNumVariants = int(sizeof(kVariants) / sizeof(kVariants[0]));
 
+// A variant fits a model of its precision whose largest block it holds; models
+// stored matrix-free take the matrix-free variants only (the others read the
+// off-diagonal matrix, which such a model does not keep on the device).
 static bool variant_fits(const Variant& v, const hyb_model* m) {
   const int want_fp64 = (m->p.precision == HYB_FP64) ? 1 : 0;
+  if (m->p.storage == HYB_MATRIX_FREE && !v.mf) return false;
+  if (v.mf && m->n_orb > 7) return false;
   return v.fp64 == want_fp64 && v.nt * v.rpt >= m->max_dim;
 }
 
@@ -197,7 +213,10 @@ static int auto_variant(const hyb_model* m) {
   for (int i = 0; i < kNumVariants; ++i) {
     const Variant& v = kVariants[i];
     if (!variant_fits(v, m)) continue;
-    const long cost = long(v.nt) * v.rpt * 4 + (v.maxm >= m->p.krylov_max ? 0 : 1000000L) + v.maxm;
+    // CSR models prefer the variants that read the matrix (matrix-free ones are picked
+    // by the autotuner when faster)
+    const long mf_cost = (v.mf && m->p.storage == HYB_CSR) ? 100000L : 0;
+    const long cost = long(v.nt) * v.rpt * 4 + (v.maxm >= m->p.krylov_max ? 0 : 1000000L) + v.maxm + mf_cost;
     if (best < 0 || cost < best_cost) {
       best = i;
       best_cost = cost;
@@ -219,9 +238,10 @@ static int dev_upload(T*& dst, const T* src, size_t n, hipStream_t s) {
 }
 
 void free_device(hyb_model* m) {
+  matrix_release(m);
   if (!m || !m->uploaded) return;
   DeviceModel& d = m->dev;
-  void* ptrs[] = {d.states, d.rank, d.blocks, d.rowptr, d.col, d.val64, d.val32, d.diag64,
+  void* ptrs[] = {d.states, d.rank, d.rank_half, d.blocks, d.rowptr, d.col, d.val64, d.val32, d.diag64,
                   d.ell_col, d.ell_val32, d.ell_perm, d.ell_len, d.tell_col, d.tell_val64, d.tell_val32, d.ret_block, d.ret_energy, d.ret_off, d.ret_vec64, d.ret_vec32, d.ws};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -267,6 +287,9 @@ static TraceParams base_params(const hyb_model* m) {
   P.eval64 = d.tell_val64;
   P.eval32 = d.tell_val32;
   P.ek = m->tell_k;
+  P.rank_half = d.rank_half;
+  P.jsf = m->p.J_sf;
+  P.jph = m->p.J_ph;
   P.ret_block = d.ret_block;
   P.ret_energy = d.ret_energy;
   P.ret_off = d.ret_off;
@@ -520,19 +543,26 @@ int hyb_model_upload(hyb_model* m, void* stream) {
   m->uploaded = true;  // so that free_device releases partial uploads
   if ((rc = dev_upload(d.states, m->states.data(), m->states.size(), s))) return rc;
   if ((rc = dev_upload(d.rank, m->rank.data(), m->rank.size(), s))) return rc;
+  if ((rc = dev_upload(d.rank_half, m->rank_half.data(), m->rank_half.size(), s))) return rc;
   if ((rc = dev_upload(d.blocks, m->blocks.data(), m->blocks.size(), s))) return rc;
-  if ((rc = dev_upload(d.rowptr, m->rowptr.data(), m->rowptr.size(), s))) return rc;
-  if ((rc = dev_upload(d.col, m->col.data(), m->col.size(), s))) return rc;
-  if ((rc = dev_upload(d.val64, m->val.data(), m->val.size(), s))) return rc;
-  if ((rc = dev_upload(d.val32, val32.data(), val32.size(), s))) return rc;
+  // the off-diagonal matrix (CSR and both ELL copies) only for CSR storage; a
+  // matrix-free model keeps one-element placeholders
+  const bool keep = m->p.storage == HYB_CSR;
+  auto up_matrix = [&](auto*& dst, const auto& v) {
+    return dev_upload(dst, keep ? v.data() : nullptr, keep ? v.size() : size_t(0), s);
+  };
+  if ((rc = up_matrix(d.rowptr, m->rowptr))) return rc;
+  if ((rc = up_matrix(d.col, m->col))) return rc;
+  if ((rc = up_matrix(d.val64, m->val))) return rc;
+  if ((rc = up_matrix(d.val32, val32))) return rc;
   if ((rc = dev_upload(d.diag64, diag_shifted.data(), diag_shifted.size(), s))) return rc;
-  if ((rc = dev_upload(d.ell_col, ell_col.data(), ell_col.size(), s))) return rc;
-  if ((rc = dev_upload(d.ell_val32, ell_val.data(), ell_val.size(), s))) return rc;
-  if ((rc = dev_upload(d.ell_perm, ell_perm.data(), ell_perm.size(), s))) return rc;
-  if ((rc = dev_upload(d.ell_len, ell_len.data(), ell_len.size(), s))) return rc;
-  if ((rc = dev_upload(d.tell_col, tell_col.data(), tell_col.size(), s))) return rc;
-  if ((rc = dev_upload(d.tell_val64, tell_val.data(), tell_val.size(), s))) return rc;
-  if ((rc = dev_upload(d.tell_val32, tell_val32.data(), tell_val32.size(), s))) return rc;
+  if ((rc = up_matrix(d.ell_col, ell_col))) return rc;
+  if ((rc = up_matrix(d.ell_val32, ell_val))) return rc;
+  if ((rc = up_matrix(d.ell_perm, ell_perm))) return rc;
+  if ((rc = up_matrix(d.ell_len, ell_len))) return rc;
+  if ((rc = up_matrix(d.tell_col, tell_col))) return rc;
+  if ((rc = up_matrix(d.tell_val64, tell_val))) return rc;
+  if ((rc = up_matrix(d.tell_val32, tell_val32))) return rc;
   if ((rc = dev_upload(d.ret_block, m->ret_block.data(), m->ret_block.size(), s))) return rc;
   if ((rc = dev_upload(d.ret_energy, m->ret_energy.data(), m->ret_energy.size(), s))) return rc;
   if ((rc = dev_upload(d.ret_off, m->ret_off.data(), m->ret_off.size(), s))) return rc;

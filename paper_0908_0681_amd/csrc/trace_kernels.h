@@ -84,6 +84,10 @@ struct TraceParams {
   const double* eval64;
   const float* eval32;
   int32_t ek;          // slots per row
+  // matrix-free rows (HYB_MATRIX_FREE and the *_mf variants): one spin's pattern ->
+  // rank among patterns of its popcount, and the spin-flip / pair-hopping amplitudes
+  const int16_t* rank_half;
+  double jsf, jph;
 };
 
 __device__ __forceinline__ int64_t cfg_end(const TraceParams& P, int c) {
@@ -201,7 +205,11 @@ __device__ __forceinline__ double to_d(VT x) { return static_cast<double>(x); }
 // the per-workgroup path evaluator
 // ---------------------------------------------------------------------------
 
-template <typename VT, int NT, int RPT, int MAXM>
+// VL: the Krylov basis V_0..V_m lives in LDS (row r of V_i at i * NT * RPT + r)
+// instead of registers; the SpMV then gathers straight from V_j.  This is the shape
+// for wide single-wave paths (many rows per lane), where a register basis would
+// spill and where several paths share a CU.
+template <typename VT, int NT, int RPT, int MAXM, bool MF = false, bool VL = false>
 struct PathEngine {
   static constexpr int NW = NT / 64;
   static constexpr int NRED = (MAXM + 2 > 16) ? MAXM + 2 : 16;  // partial sums per reduction round
@@ -225,15 +233,21 @@ struct PathEngine {
   // Off-diagonal slots of each thread's rows held in LDS during a propagation, up to
   // KL per row within a per-variant budget (rows with more entries use the CSR in HBM)
   static constexpr int NR = NT * RPT;
-  static constexpr int SLAB_BYTES = (NT >= 512) ? 64 * 1024 : (NT >= 256) ? 96 * 1024 : 10 * 1024 * (NT / 64);
+  // LDS budget for staged rows: none for matrix-free rows and for wide single-wave
+  // paths (RPT > 4: those read their rows from L2 at every SpMV so that several paths
+  // share a CU)
+  static constexpr int SLAB_BYTES = (MF || (NT == 64 && RPT > 4)) ? 0
+                                    : (NT >= 512) ? 64 * 1024 : (NT >= 256) ? 96 * 1024 : 10 * 1024 * (NT / 64);
   static constexpr int KL0 = SLAB_BYTES / (NR * int(sizeof(VT) + sizeof(int16_t)));
   static constexpr int KL = KL0 > 16 ? 16 : KL0;
   struct Smem {
-    VT vec[NT * RPT];
+    VT vec[VL ? 1 : NT * RPT];
+    VT vb[VL ? (MAXM + 1) * NT * RPT : 1];  // the Krylov basis when VL
     double red[2][NW][NRED];
     Small small[NW];
     VT sval[KL > 0 ? KL * NR : 1];       // slot q of local row r at q * NR + r
     int16_t scol[KL > 0 ? KL * NR : 1];
+    int16_t rh[MF ? 128 : 1];            // matrix-free: rank_half of the model (2^n_orb <= 128)
   };
 
   const TraceParams& P;
@@ -243,6 +257,8 @@ struct PathEngine {
 
   __device__ PathEngine(const TraceParams& p, Smem& s)
       : P(p), S(s), tid(threadIdx.x), lane(threadIdx.x & 63), wid(threadIdx.x >> 6) {}
+
+  uint32_t rstate[MF ? RPT : 1];  // matrix-free: the basis state of each of this thread's rows
 
   __device__ __forceinline__ const VT* ret_vec() const {
     if constexpr (sizeof(VT) == 8) return reinterpret_cast<const VT*>(P.ret_vec64);
@@ -302,35 +318,111 @@ struct PathEngine {
 
   __device__ __forceinline__ int row(int k) const { return tid + k * NT; }
 
-  // y = (H_b - c_b) x for the rows owned by this thread.  x is staged in LDS.
-  // y = (H_b - c_b) x.  The vector is shared through LDS; each thread's rows come
-  // from its own LDS slots when staged (stage_rows), else from the CSR in HBM.
+  // Off-diagonal part of row t of H_b applied to the vector in S.vec, generated from
+  // t's bits (Eq.(4), each ordered orbital pair a != c once): spin flip
+  // -J_sf c+_{a dn} c+_{c up} c_{c dn} c_{a up} needs a singly occupied by up and c
+  // by down; pair hopping -J_ph c+_{c up} c+_{c dn} c_{a up} c_{a dn} needs a doubly
+  // occupied and c empty.  Both flip orbitals a and c in both spin strings; the sign
+  // is the Jordan-Wigner parity of the four operators applied right to left.  The
+  // target's index inside the block is rank_half[dn'] * up_states + rank_half[up'].
+  __device__ __forceinline__ double row_free(const BlockDev& B, uint32_t t, const VT* xs) const {
+    const int n = P.n_orb;
+    const uint32_t lo = (1u << n) - 1u;
+    const uint32_t up = t & lo, dn = t >> n;
+    VT sf = VT(0), ph = VT(0);
+    auto parity_step = [](uint32_t& cur, uint32_t bit) {
+      const int par = __popc(cur & (bit - 1u)) & 1;
+      cur ^= bit;
+      return par;
+    };
+    auto take = [&](uint32_t t2) {
+      return xs[int(S.rh[t2 >> n]) * B.up_states + int(S.rh[t2 & lo])];
+    };
+    if (P.jsf != 0.0) {
+      for (uint32_t ma = up & ~dn; ma; ma &= ma - 1u) {
+        const int a = __ffs(ma) - 1;
+        for (uint32_t mc = dn & ~up; mc; mc &= mc - 1u) {
+          const int c = __ffs(mc) - 1;
+          uint32_t cur = t;
+          int par = parity_step(cur, 1u << a);
+          par ^= parity_step(cur, 1u << (c + n));
+          par ^= parity_step(cur, 1u << c);
+          par ^= parity_step(cur, 1u << (a + n));
+          const VT v = take(cur);
+          sf += par ? -v : v;
+        }
+      }
+    }
+    if (P.jph != 0.0) {
+      for (uint32_t ma = up & dn; ma; ma &= ma - 1u) {
+        const int a = __ffs(ma) - 1;
+        for (uint32_t mc = lo & ~(up | dn); mc; mc &= mc - 1u) {
+          const int c = __ffs(mc) - 1;
+          uint32_t cur = t;
+          int par = parity_step(cur, 1u << (a + n));
+          par ^= parity_step(cur, 1u << a);
+          par ^= parity_step(cur, 1u << (c + n));
+          par ^= parity_step(cur, 1u << c);
+          const VT v = take(cur);
+          ph += par ? -v : v;
+        }
+      }
+    }
+    return -P.jsf * to_d(sf) - P.jph * to_d(ph);
+  }
+
+  // y = (H_b - c_b) x for the rows owned by this thread.  The whole vector is read
+  // from LDS: from xsrc when it is there already (the basis of VL engines), else
+  // after staging x into S.vec.  Each thread's rows come from its own LDS slots when
+  // staged (stage_rows), from the ELL copy in L2 when the variant keeps no slots,
+  // from the CSR in HBM otherwise, or are generated from the bits (MF).
   __device__ __forceinline__ void spmv(const BlockDev& B, const VT (&x)[RPT], VT (&y)[RPT],
-                                       const double (&dg)[RPT], bool staged) {
+                                       const double (&dg)[RPT], bool staged, const VT* xsrc = nullptr) {
+    const VT* xs = xsrc;
+    if (!xs) {
 #pragma unroll
-    for (int k = 0; k < RPT; ++k)
-      if (row(k) < B.dim) S.vec[row(k)] = x[k];
+      for (int k = 0; k < RPT; ++k)
+        if (row(k) < B.dim) S.vec[row(k)] = x[k];
+      xs = S.vec;
+    }
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
       const int r = row(k);
       if (r < B.dim) {
         VT acc = VT(0);
+        if constexpr (MF) {
+          y[k] = static_cast<VT>(dg[k] * to_d(x[k]) + row_free(B, rstate[k], xs));
+          continue;
+        }
         if (staged) {
           const int K = P.ek;
 #pragma unroll 2
-          for (int q = 0; q < K; ++q) acc += S.sval[q * NR + r] * S.vec[S.scol[q * NR + r]];
+          for (int q = 0; q < K; ++q) acc += S.sval[q * NR + r] * xs[S.scol[q * NR + r]];
+        } else if constexpr (KL == 0) {
+          // the block's natural-order ELL rows straight from global memory (L2): slot q
+          // of row r at state_off * K + q * dim + r, so a wave's loads are contiguous
+          const int K = P.ek;
+          const int64_t base = int64_t(B.state_off) * K + r;
+#pragma unroll 4
+          for (int q = 0; q < K; ++q) {
+            const int64_t at = base + int64_t(q) * B.dim;
+            VT v;
+            if constexpr (sizeof(VT) == 8) v = static_cast<VT>(P.eval64[at]);
+            else v = static_cast<VT>(P.eval32[at]);
+            acc += v * xs[P.ecol[at]];
+          }
         } else {
           const int g = B.state_off + r;
           const int j0 = P.rowptr[g], j1 = P.rowptr[g + 1];
-          for (int j = j0; j < j1; ++j) acc += offval(j) * S.vec[P.col[j]];
+          for (int j = j0; j < j1; ++j) acc += offval(j) * xs[P.col[j]];
         }
         y[k] = static_cast<VT>(dg[k] * to_d(x[k]) + to_d(acc));
       } else {
         y[k] = VT(0);
       }
     }
-    __syncthreads();  // S.vec is rewritten by the next staging
+    __syncthreads();  // the source is rewritten by the next staging / basis update
   }
 
   // Loads the diagonal of this thread's rows of block B into registers and, when
@@ -344,6 +436,16 @@ struct PathEngine {
     for (int k = 0; k < RPT; ++k) {
       const int r = row(k);
       dg[k] = (r < B.dim) ? P.diag64[B.state_off + r] : 0.0;
+    }
+    if constexpr (MF) {
+#pragma unroll
+      for (int k = 0; k < RPT; ++k) {
+        const int r = row(k);
+        rstate[k] = (r < B.dim) ? P.states[B.state_off + r] : 0u;
+      }
+      // read after the barrier of the first SpMV's vector staging
+      for (int i = tid; i < (1 << P.n_orb); i += NT) S.rh[i] = P.rank_half[i];
+      return false;
     }
 #pragma unroll 1
     for (int k = 0; k < RPT; ++k) {
@@ -839,27 +941,38 @@ struct PathEngine {
     double dg[RPT];
     const bool staged = stage_rows(B, dg);
     double remaining = dtau;
-    VT V[MAXM + 1][RPT];
+    VT V[VL ? 1 : MAXM + 1][RPT];
+    // element (i, k) of the basis: V_i at this thread's k-th row
+    auto VA = [&](int i, int k) -> VT& {
+      if constexpr (VL) return S.vb[i * NR + row(k)];
+      else return V[i][k];
+    };
     for (int nsub = 0; remaining > 0.0; ++nsub) {
       if (nsub > P.max_substeps) {
         atomicOr(&P.counters[2], ERR_NOCONV);
         return false;
       }
 #pragma unroll
-      for (int k = 0; k < RPT; ++k) V[0][k] = x[k];
+      for (int k = 0; k < RPT; ++k) VA(0, k) = x[k];
       int m = 0;
       double tau_used = remaining, theta_min = 0.0, ynorm = 1.0, yv = 0.0, tscale = 0.0;
       for (int j = 0; j < kmax; ++j) {
         VT vj[RPT], w[RPT];
+        if constexpr (VL) {
 #pragma unroll
-        for (int k = 0; k < RPT; ++k) vj[k] = V[0][k];
+          for (int k = 0; k < RPT; ++k) vj[k] = VA(j, k);
+          spmv(B, vj, w, dg, staged, S.vb + j * NR);
+        } else {
 #pragma unroll
-        for (int i = 1; i < MAXM; ++i)
-          if (i == j) {
+          for (int k = 0; k < RPT; ++k) vj[k] = V[0][k];
 #pragma unroll
-            for (int k = 0; k < RPT; ++k) vj[k] = V[i][k];
-          }
-        spmv(B, vj, w, dg, staged);
+          for (int i = 1; i < MAXM; ++i)
+            if (i == j) {
+#pragma unroll
+              for (int k = 0; k < RPT; ++k) vj[k] = V[i][k];
+            }
+          spmv(B, vj, w, dg, staged);
+        }
         // classical Gram-Schmidt twice against V_0..V_j; the second round also
         // reduces ||w||^2 so that beta_j needs no extra round
         double hj;
@@ -871,7 +984,7 @@ struct PathEngine {
           for (int i = 0; i < MAXM; ++i)
             if (i <= j) {
 #pragma unroll
-              for (int k = 0; k < RPT; ++k) h[i] += to_d(V[i][k]) * to_d(w[k]);
+              for (int k = 0; k < RPT; ++k) h[i] += to_d(VA(i, k)) * to_d(w[k]);
             }
           block_sum<NRED>(h, j + 1);
 #pragma unroll
@@ -879,7 +992,7 @@ struct PathEngine {
             double t = to_d(w[k]);
 #pragma unroll
             for (int i = 0; i < MAXM; ++i)
-              if (i <= j) t -= h[i] * to_d(V[i][k]);
+              if (i <= j) t -= h[i] * to_d(VA(i, k));
             w[k] = static_cast<VT>(t);
           }
           hj = h[0];
@@ -898,7 +1011,7 @@ struct PathEngine {
             const double wd = to_d(w[k]);
 #pragma unroll
             for (int i = 0; i < MAXM; ++i)
-              if (i <= j) h[i] += to_d(V[i][k]) * wd;
+              if (i <= j) h[i] += to_d(VA(i, k)) * wd;
             wn += wd * wd;
           }
 #pragma unroll
@@ -917,7 +1030,7 @@ struct PathEngine {
             double t = to_d(w[k]);
 #pragma unroll
             for (int i = 0; i < MAXM; ++i)
-              if (i <= j) t -= h[i] * to_d(V[i][k]);
+              if (i <= j) t -= h[i] * to_d(VA(i, k));
             w[k] = static_cast<VT>(t);
           }
           double h2j = h[0];
@@ -987,7 +1100,7 @@ struct PathEngine {
         for (int i = 1; i <= MAXM; ++i)
           if (i == j + 1) {
 #pragma unroll
-            for (int k = 0; k < RPT; ++k) V[i][k] = static_cast<VT>(to_d(w[k]) * inv);
+            for (int k = 0; k < RPT; ++k) VA(i, k) = static_cast<VT>(to_d(w[k]) * inv);
           }
       }
       // recombination x = V_m y / ||y||
@@ -997,7 +1110,7 @@ struct PathEngine {
         double t = 0.0;
 #pragma unroll
         for (int i = 0; i < MAXM; ++i)
-          if (i < m) t += readlane_d(yv, i) * to_d(V[i][k]);
+          if (i < m) t += readlane_d(yv, i) * to_d(VA(i, k));
         x[k] = static_cast<VT>(t * inv);
       }
       ell += -tau_used * (shift + theta_min) + log(ynorm);
@@ -1197,9 +1310,10 @@ __device__ inline void path_op(const TraceParams& P, int w, int k, double* red) 
 }
 
 // Step 5: Krylov propagation of the path's vector over tau_k - tau_{k-1}, in place.
-template <typename VT, int NT, int RPT, int MAXM>
-__device__ inline void path_prop(const TraceParams& P, int w, int k, typename PathEngine<VT, NT, RPT, MAXM>::Smem& S) {
-  using E = PathEngine<VT, NT, RPT, MAXM>;
+template <typename VT, int NT, int RPT, int MAXM, bool MF, bool VL>
+__device__ inline void path_prop(const TraceParams& P, int w, int k,
+                                 typename PathEngine<VT, NT, RPT, MAXM, MF, VL>::Smem& S) {
+  using E = PathEngine<VT, NT, RPT, MAXM, MF, VL>;
   if (P.st_status[w] != PATH_ACTIVE) return;
   const int id = P.work[w];
   const int c = id / P.n_ret;

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libhyb.so")
 HYB_OK = 0
 ERRORS = {-1: "HYB_E_ARG", -2: "HYB_E_UNSORTED", -3: "HYB_E_FLAVOR", -4: "HYB_E_NOCONV",
           -5: "HYB_E_NONFINITE", -6: "HYB_E_HIP", -7: "HYB_E_OOM", -8: "HYB_E_STATE"}
-HYB_CSR = 0
+HYB_CSR, HYB_MATRIX_FREE = 0, 1
 HYB_FP64, HYB_MIXED = 0, 1
 
 
@@ -94,6 +94,9 @@ _SIGS = {
     "hyb_set_timing": (C.c_int, [_P, C.c_int32]),
     "hyb_last_timing": (C.c_int, [_P, _P]),
     "hyb_block_spmm": (C.c_int, [_P, C.c_int32, C.c_int64, _P, _P, _P]),
+    "hyb_matrix_build": (C.c_int, [_P, _P]),
+    "hyb_matrix_info": (C.c_int, [_P, _P, _P]),
+    "hyb_trace_batch_matrix": (C.c_int, [_P, C.POINTER(ConfigBatchC), C.c_double, C.POINTER(TraceOutC), _P]),
     "hyb_mc_create": (C.c_int, [_P, C.POINTER(McParamsC), C.POINTER(_P)]),
     "hyb_mc_destroy": (C.c_int, [_P]),
     "hyb_mc_set_configs": (C.c_int, [_P, _P, _P, _P, _P]),
@@ -190,14 +193,15 @@ class Model:
     """Owns a hyb_model handle."""
 
     def __init__(self, params, precision="fp64", retain_window=1e-5, krylov_max=12,
-                 krylov_tol=None, upload=True, stream=None):
+                 krylov_tol=None, upload=True, stream=None, storage="csr"):
         prec = {"fp64": HYB_FP64, "mixed": HYB_MIXED}[precision]
+        store = {"csr": HYB_CSR, "matrix_free": HYB_MATRIX_FREE}[storage]
         if krylov_tol is None:
             krylov_tol = 1e-13 if prec == HYB_FP64 else 1e-7
         self._eps = np.ascontiguousarray(params.eps, dtype=np.float64)
         p = ModelParamsC(n_orb=params.n_orb, eps=self._eps.ctypes.data_as(C.POINTER(C.c_double)),
                          U=params.U, Up=params.Up, J=params.J, J_sf=params.J_sf, J_ph=params.J_ph,
-                         storage=HYB_CSR, precision=prec, retain_window=retain_window,
+                         storage=store, precision=prec, retain_window=retain_window,
                          krylov_max=krylov_max, krylov_tol=krylov_tol)
         h = C.c_void_p()
         _check(lib().hyb_model_create(C.byref(p), C.byref(h)))
@@ -348,6 +352,33 @@ class Model:
         device workspace instead of an allocated one."""
         cfg, o = self._device_args(dev_batch, out)
         _check(lib().hyb_trace_batch_noalloc(self.h, C.byref(cfg), beta, C.byref(o), _stream(stream)))
+
+    def matrix_build(self, stream=None):
+        """hyb_matrix_build: the eigenbasis operator blocks of the matrix formulation."""
+        _check(lib().hyb_matrix_build(self.h, _stream(stream)))
+
+    def matrix_info(self):
+        nb, sec = C.c_int64(), C.c_double()
+        _check(lib().hyb_matrix_info(self.h, C.byref(nb), C.byref(sec)))
+        return {"op_bytes": nb.value, "build_seconds": sec.value}
+
+    def trace_batch_matrix(self, batch, beta=None, stream=None):
+        """Host batch -> TraceResult by the matrix formulation (hyb_trace_batch_matrix)."""
+        beta = batch.beta if beta is None else beta
+        n = batch.n_configs
+        cfg = ConfigBatchC(n_configs=n, offsets=_ptr(batch.offsets), tau=_ptr(batch.tau),
+                           flavor=_ptr(batch.flavor), dagger=_ptr(batch.dagger), on_device=0)
+        res = TraceResult(np.zeros(n, np.int8), np.zeros(n), np.zeros(n, np.int32), np.zeros(n, np.int32),
+                          np.zeros(n, np.int32), np.zeros(n, np.int64), np.zeros(n, np.int64))
+        out = TraceOutC(log_abs=_ptr(res.log_abs), sign=_ptr(res.sign), krylov_steps=_ptr(res.krylov_steps),
+                        substeps=_ptr(res.substeps), feasible_paths=_ptr(res.feasible_paths),
+                        rowsteps=_ptr(res.rowsteps), rows=_ptr(res.rows), on_device=0)
+        _check(lib().hyb_trace_batch_matrix(self.h, C.byref(cfg), beta, C.byref(out), _stream(stream)))
+        return res
+
+    def trace_batch_matrix_device(self, dev_batch, beta, out, stream=None):
+        cfg, o = self._device_args(dev_batch, out)
+        _check(lib().hyb_trace_batch_matrix(self.h, C.byref(cfg), beta, C.byref(o), _stream(stream)))
 
     def block_spmm(self, b, X, Y, n_vec, stream=None):
         _check(lib().hyb_block_spmm(self.h, b, n_vec, _ptr(X), _ptr(Y), _stream(stream)))

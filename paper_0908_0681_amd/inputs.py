@@ -204,6 +204,16 @@ def workload(k: int) -> Workload:
     raise ValueError(k)
 
 
+def comparator_workload(n_orb: int, n_configs: int = 512) -> Workload:
+    """The Krylov-against-matrix comparison of Sec. IV.B: n_orb = 2..7 orbitals at
+    U = 6, J = U/6, half filling (mu_half), beta = 50, a crystal field of +-0.05,
+    per-flavor orders ~ Poisson(5), the ground multiplet retained; FP64."""
+    U, J = 6.0, 1.0
+    p = kanamori(n_orb, U=U, J=J, mu=mu_half(n_orb, U, J), delta=crystal_field(n_orb, 0.05, MODEL_SEED))
+    return Workload(f"kanamori-{n_orb}orb-U6-b50", p, 50.0, n_configs, 5.0, 1100 + n_orb, "fp64", 1e-5,
+                    krylov_max=20, krylov_tol=1e-13)
+
+
 # --------------------------------------------------------------------------
 # bath and Monte Carlo inputs
 # --------------------------------------------------------------------------

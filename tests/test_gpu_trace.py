@@ -316,6 +316,50 @@ def test_full_size_seven_orbital_sampled(w2):
     assert np.all(r.feasible_paths >= 1) and np.all(np.isin(r.sign, (-1, 0, 1)))
 
 
+@pytest.mark.parametrize("k,n", [(0, 64), (1, 64), (2, 12)])
+def test_matrix_free_storage_parity(k, n):
+    """HYB_MATRIX_FREE: no off-diagonal matrix on the device, the kernels generate each
+    row's spin-flip and pair-hopping entries from its bits; same bars as CSR."""
+    _require_gpu()
+    w = I.workload(k)
+    m = hyb.model_for_workload(w, use_cache=False, storage="matrix_free")
+    assert hyb.variant_names()[m.variant()].endswith("_mf")
+    b = w.batch(n)
+    if k == 2:
+        ref, _ = OP.trace_batch(w.params, w.retain_window, b)
+        o = T.build(w.params, w.retain_window)
+        worst, esc = compare(m.trace_batch(b), ref, 1e-5, o, b, unit=U32)
+    else:
+        o = T.build(w.params, w.retain_window)
+        worst, esc = compare(m.trace_batch(b), o.trace_batch(b), 1e-10, o, b)
+    assert esc == 0
+    print(f"matrix-free {w.name}: worst relative error {worst:.3e}")
+    if k > 0:
+        X = torch.zeros(16 * m.info()["max_dim"], device="cuda")
+        with pytest.raises(hyb.HybError) as e:
+            m.block_spmm(0, X, X, 16)
+        assert e.value.code == -8
+
+
+def test_every_variant_agrees_seven_orbital(w2):
+    """Every FP32 kernel variant that holds the 7-orbital blocks, against the oracle."""
+    w, m, o = w2
+    b = w.batch(12)
+    ref, _ = OP.trace_batch(w.params, w.retain_window, b)
+    tried = 0
+    for v, name in enumerate(hyb.variant_names()):
+        try:
+            m.set_variant(v)
+        except hyb.HybError:
+            continue
+        tried += 1
+        worst, esc = compare(m.trace_batch(b), ref, 1e-5, o, b, unit=U32)
+        assert esc == 0, name
+        print(f"{name}: worst relative error {worst:.3e}")
+    m.set_variant(-1)
+    assert tried >= 4
+
+
 @pytest.mark.parametrize("k", [1, 2])
 def test_chunked_schedule_identical(k):
     """One launch per step, per chunk of operators, or per whole path: the same

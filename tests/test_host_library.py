@@ -146,3 +146,33 @@ def test_model_argument_errors():
     with pytest.raises(hyb.HybError) as e:
         hyb.Model(nanp, upload=False)
     assert e.value.code == -5
+
+
+def test_matrix_free_index_formula():
+    """The matrix-free kernels index a state (up, dn) inside its block as
+    rank(dn) * C(n, n_up) + rank(up), rank = position among the one-spin patterns of
+    the same popcount in ascending order.  That equals the library's basis index
+    for every state of the 5-orbital model (CPU, through the host parity hook)."""
+    from math import comb
+    n = 5
+    m = hyb.Model(I.workload(1).params, upload=False, storage="matrix_free")
+    rank = {}
+    seen = {}
+    for x in range(1 << n):
+        c = bin(x).count("1")
+        rank[x] = seen.get(c, 0)
+        seen[c] = rank[x] + 1
+    for s in range(1 << (2 * n)):
+        up, dn = s & ((1 << n) - 1), s >> n
+        b, idx = m.basis_index(s)
+        assert idx == rank[dn] * comb(n, bin(up).count("1")) + rank[up], s
+
+
+def test_storage_argument():
+    p = I.workload(0).params
+    hyb.Model(p, upload=False, storage="matrix_free").close()
+    C = hyb.ModelParamsC(n_orb=2, eps=np.zeros(2).ctypes.data_as(hyb.C.POINTER(hyb.C.c_double)), U=1.0, Up=1.0,
+                         J=0.0, J_sf=0.0, J_ph=0.0, storage=7, precision=0, retain_window=-1.0, krylov_max=12,
+                         krylov_tol=1e-12)
+    h = hyb.C.c_void_p()
+    assert hyb.lib().hyb_model_create(hyb.C.byref(C), hyb.C.byref(h)) == -1
