@@ -292,13 +292,6 @@ def measure_spmm(torch, hyb, I, n_vec=262144, reps=10):
     return out
 
 
-def _g_half(mc, beta, n_tau):
-    """Per chain: the sign-weighted flavor average of G(tau) over the two bins at beta/2."""
-    g, ms, nm = mc.accumulators()
-    G = -g / (beta * (beta / n_tau) * ms[:, None, None])
-    return G[:, :, n_tau // 2 - 1:n_tau // 2 + 1].mean(axis=(1, 2)), nm
-
-
 def _sg_half(g, nm, beta, n_tau):
     """Per chain: the sign-weighted measurement s*G at beta/2 (flavor average of the
     two bins) averaged over nm measurements; no division by the sign sum, so chains
@@ -312,7 +305,8 @@ def _sg_half(g, nm, beta, n_tau):
 def _robust_var(x):
     """Variance of a sample from its median absolute deviation, (1.4826 MAD)^2, which
     equals the variance for normal data and ignores a few outlying values; also the
-    number of values more than 5 such standard deviations from the median."""
+    number of values more than 5 such standard deviations from the median.  A
+    diagnostic only: outlying chains are real slow-mixing variance."""
     import numpy as np
     x = np.asarray(x, dtype=np.float64)
     med = np.median(x)
@@ -320,67 +314,125 @@ def _robust_var(x):
     return float(sd * sd), int(np.sum(np.abs(x - med) > 5.0 * sd)) if sd > 0 else 0
 
 
-def _g_blocks(mc, beta, n_tau, n_blocks, moves):
-    """Per chain and block: the mean of s*G(beta/2) over each block of moves / n_blocks
-    moves, and the chains' totals of s*G and s over all blocks."""
+def _ratio_jackknife(sg, s):
+    """The sign-weighted estimate G = sum_c sg_c / sum_c s_c over independent chains c
+    (sg: [C] or [C, k] per-chain sums of s*G, s: [C] per-chain sums of the sign) and
+    its delete-one-chain jackknife standard error.  Chains are independent, so this
+    error holds whatever the autocorrelation inside a chain."""
     import numpy as np
-    per = moves // n_blocks
-    out = []
-    g0, ms0, nm0 = mc.accumulators()
-    gs, ms_start = g0, ms0
-    for bi in range(n_blocks):
-        mc.sweep(per)
-        if per >= 500:
-            print(f"[ess] block {bi + 1}/{n_blocks} of {per} moves", file=sys.stderr, flush=True)
-        g1, ms1, nm1 = mc.accumulators()
-        out.append(_sg_half(g1 - g0, nm1 - nm0, beta, n_tau))
-        g0, ms0, nm0 = g1, ms1, nm1
-    return np.stack(out, axis=1), _sg_half(g0 - gs, 1, beta, n_tau), ms0 - ms_start
+    sg = np.asarray(sg, dtype=np.float64)
+    s = np.asarray(s, dtype=np.float64)
+    C = s.shape[0]
+    SG, S = sg.sum(axis=0), s.sum()
+    sh = s.reshape((C,) + (1,) * (sg.ndim - 1))
+    loo = (SG[None] - sg) / (S - sh)
+    se = np.sqrt((C - 1) / C * np.sum((loo - loo.mean(axis=0)) ** 2, axis=0))
+    return SG / S, se
 
 
-def _thermalise(mc, chunk=1000, min_moves=10000, max_moves=40000, rtol=0.003):
-    """Uniform sweeps until the mean expansion order over the chains changes by less
-    than rtol between consecutive chunks (the chains start at orders spread over
-    0..200, far from equilibrium).  Returns the moves spent and the last mean order."""
+def _drift_t(prev, cur):
+    """t statistic of the change of per-chain means between two consecutive chunks
+    (independent chains: the mean change over its standard error)."""
     import numpy as np
-    done, prev = 0, None
+    d = np.asarray(cur, dtype=np.float64) - np.asarray(prev, dtype=np.float64)
+    sd = np.std(d, ddof=1)
+    return float(np.mean(d) / (sd / np.sqrt(len(d)))) if sd > 0 else 0.0
+
+
+def _heldout_gain(logits, targets, beta, eps, bins=64):
+    """Mean log-likelihood gain over uniform insertion, in nats per pair, of held-out
+    (tau_s bin, length bin) targets: log(beta^2 q) with the mixture density
+    q = (1 - eps) p_tau (bins/beta) p_l (bins/beta) + eps/beta^2, and the network's
+    own gain log(bins^2 p_tau p_l) without the uniform floor."""
+    import numpy as np
+    z = np.asarray(logits, dtype=np.float64)
+    t = np.asarray(targets)
+
+    def logp(zz, k):
+        m = zz.max(axis=1, keepdims=True)
+        lse = m[:, 0] + np.log(np.exp(zz - m).sum(axis=1))
+        return zz[np.arange(len(k)), k] - lse
+
+    lp = logp(z[:, :bins], t[:, 0]) + logp(z[:, bins:2 * bins], t[:, 1])
+    net = lp + 2.0 * np.log(bins)
+    mix = np.log((1.0 - eps) * np.exp(net) + eps)
+    return float(mix.mean()), float(net.mean())
+
+
+def _two_sample(a, se_a, b, se_b):
+    """z per bin of two independent estimates of a curve; chi^2 per degree of freedom
+    and the largest |z|."""
+    import numpy as np
+    z = (np.asarray(a) - np.asarray(b)) / np.sqrt(np.asarray(se_a) ** 2 + np.asarray(se_b) ** 2)
+    return float(np.mean(z ** 2)), float(np.max(np.abs(z)))
+
+
+def _chain_sums(mc, beta, n_tau):
+    """Per chain: sums over the measurements of s*G(tau) (flavor average, [C, n_tau]),
+    of s*G(beta/2) (the two middle bins) and of the sign."""
+    g, ms, nm = mc.accumulators()
+    sg = (-g / (beta * (beta / n_tau))).mean(axis=1)
+    return sg, sg[:, n_tau // 2 - 1:n_tau // 2 + 1].mean(axis=1), ms, nm
+
+
+def _thermalise(mc, beta, n_tau, chunk=1000, min_moves=6000, max_moves=30000):
+    """Uniform sweeps in chunks until the mean expansion order and s*G(beta/2) are
+    stationary: the per-chain chunk means change by less than two standard errors
+    (|t| < 2 for both) at two consecutive checks, after at least min_moves moves (the
+    chains start at orders spread over 0..200).  Returns the record of the gate."""
+    import numpy as np
+    done, prev, ok_run, hist = 0, None, 0, []
     while done < max_moves:
+        mc.reset_measurements()
         mc.sweep(chunk)
         done += chunk
-        order = float(np.mean(mc.state()["k"].sum(axis=1)))
-        print(f"[ess] thermalising: {done} moves, mean order {order:.2f}", file=sys.stderr, flush=True)
-        if done >= min_moves and prev is not None and abs(order - prev) <= rtol * max(prev, 1.0):
-            break
-        prev = order
-    return done, order
+        _, sgh, _, nm = _chain_sums(mc, beta, n_tau)
+        order = mc.state()["k"].sum(axis=1).astype(np.float64)
+        cur = (order, sgh / np.maximum(nm, 1))
+        if prev is not None:
+            t_o, t_g = _drift_t(prev[0], cur[0]), _drift_t(prev[1], cur[1])
+            hist.append((done, float(order.mean()), t_o, t_g))
+            ok_run = ok_run + 1 if (abs(t_o) < 2.0 and abs(t_g) < 2.0) else 0
+            print(f"[ess] thermalising: {done} moves, mean order {order.mean():.2f}, t(order) {t_o:+.2f}, "
+                  f"t(G(beta/2)) {t_g:+.2f}", file=sys.stderr, flush=True)
+            if done >= min_moves and ok_run >= 2:
+                break
+        prev = cur
+    return {"moves": done, "stationary": ok_run >= 2, "mean_order": hist[-1][1] if hist else None,
+            "last_t_order": hist[-1][2] if hist else None, "last_t_g_half": hist[-1][3] if hist else None,
+            "chunk": chunk}
 
 
-def measure_ess(torch, hyb, I, harvests=100, train_steps=1000, moves=20000, n_tau=20, eps=0.1,
-                n_blocks=20, snapshots=4, seed_offset=0):
-    """Effective samples per second of G(beta/2), learned vs uniform insertion, on the
-    5-orbital model with the semicircular bath (256 chains).  Both samplers start from
-    the same thermalised uniform-sampler state.  ESS = n_chains * var1 / var(chain mean),
-    with var1 the variance of a single measurement (one move), pooled over snapshots
-    of both samplers (a property of the distribution, not of the sampler), and
-    var(chain mean) estimated three ways:
-    - across chains (headline): the spread of the 256 chain means from their median
-      absolute deviation, (1.4826 MAD)^2, so that a few outlying chains do not decide
-      it (the only estimate for runs not much longer than the autocorrelation time);
-    - across chains, plain: the sample variance of the chain means (reported beside it;
-      one outlying chain can change it tenfold);
-    - blocking: the run as n_blocks blocks, var(block means) / n_blocks per chain,
-      averaged over chains (valid once a block is much longer than the
-      autocorrelation time).
-    The observable is the sign-weighted measurement s*G(beta/2) (G = <sG>/<s>, reported
-    as the pooled ratio over all chains).  Both samplers start from the same
-    uniform-sampler state, thermalised until the mean expansion order is stationary.
-    Wall time includes the network's inference.  The network is trained beforehand on
-    pairs harvested from the uniform chains (time reported separately)."""
+def measure_ess(torch, hyb, I, pairs=1_000_000, target_se=1e-3, max_moves=12000, chunk=2000, n_tau=20, eps=0.1,
+                seed_offset=0, train_steps=3000, batch=1024, lr=2e-3, therm=(6000, 30000)):
+    """Learned against uniform insertion on the 5-orbital model with the semicircular
+    bath (256 chains), measured as the wall time to reach one target standard error of
+    G(beta/2).
+    - Thermalisation: uniform moves until the mean order and s*G(beta/2) pass the
+      stationarity gate of _thermalise.
+    - Training set: about `pairs` (creator, annihilator) pairs harvested from the
+      thermalised uniform chains (one per chain after every move); 10% held out, on
+      which the learned density's log-likelihood gain over uniform is reported (nats
+      per pair).
+    - Both samplers then start from the same thermalised state and run in chunks of
+      `chunk` moves until the jackknife-over-chains standard error of G(beta/2) (the
+      pooled sign-weighted ratio; chains are independent, so the error holds whatever
+      the autocorrelation) is at most target_se, or max_moves is reached.  Wall time
+      counts the sweeps only (network inference included), not the error checks.
+    - Headline: time_uniform / time_learned to the target, each projected from where
+      the run stopped as t * (se / target)^2 (the error falls as 1/sqrt(t)), so that a
+      target met inside a chunk, or missed at max_moves, is not rounded to the chunk.
+      ESS = var1 / se^2 (var1: the pooled variance of one measurement) per sampler.
+    - Diagnostics only: the plain and MAD-based variance of the chain means and the
+      number of outlying chains.
+    - Agreement: a two-sample test of the two G(tau) curves (jackknife errors)."""
+    import math
     import numpy as np
     setup = I.mc_setup(3)
     w = setup.workload
     m = hyb.model_for_workload(w)
-    mk = lambda seed: hyb.MC(m, setup.n_chains, w.beta, setup.delta, kmax=setup.kmax_flavor, nmax_ops=512,
+    C = setup.n_chains
+    mk = lambda seed: hyb.MC(m, C, w.beta, setup.delta, kmax=setup.kmax_flavor, nmax_ops=512,
                              seed=seed, n_tau=n_tau, meas_every=1)
     F = 2 * w.params.n_orb
     chains = I.mc_initial_configs(setup)
@@ -388,80 +440,101 @@ def measure_ess(torch, hyb, I, harvests=100, train_steps=1000, moves=20000, n_ta
     chains = [ch if r.sign[c] != 0 else ([[]] * F, [[]] * F) for c, ch in enumerate(chains)]
     base = mk(setup.seed + 100 * seed_offset)
     base.set_configs(chains)
-    therm, therm_order = _thermalise(base)
-    # training pairs from the uniform chains
+    th = _thermalise(base, w.beta, n_tau, min_moves=therm[0], max_moves=therm[1])
+    # training pairs from the thermalised uniform chains, one per chain and move
     t0 = time.perf_counter()
-    Xs, Ts = [], []
-    for hv in range(harvests):
-        X = torch.zeros(setup.n_chains, hyb.MLP_IN, device="cuda", dtype=torch.bfloat16)
-        T = torch.zeros(setup.n_chains, 2, device="cuda", dtype=torch.int32)
-        base.harvest(hv, X, T)
-        base.sweep(2)
-        Xs.append(X)
-        Ts.append(T)
-    X, T = torch.cat(Xs), torch.cat(Ts)
+    n_h = int(math.ceil(pairs / C))
+    X = torch.zeros(n_h * C, hyb.MLP_IN, device="cuda", dtype=torch.bfloat16)
+    T = torch.zeros(n_h * C, 2, device="cuda", dtype=torch.int32)
+    for hv in range(n_h):
+        base.harvest(hv, X[hv * C:(hv + 1) * C], T[hv * C:(hv + 1) * C])
+        base.sweep(1)
+        if hv % 1000 == 999:
+            print(f"[ess] harvested {(hv + 1) * C} pairs", file=sys.stderr, flush=True)
+    harvest_s = time.perf_counter() - t0
     keep = T[:, 0] >= 0
     X, T = X[keep].contiguous(), T[keep].contiguous()
-    net = hyb.MLP(seed=2024)
     gen = torch.Generator(device="cuda").manual_seed(7)
+    perm = torch.randperm(X.shape[0], device="cuda", generator=gen)
+    n_hold = X.shape[0] // 10
+    hold, train = perm[:n_hold], perm[n_hold:]
+    t1 = time.perf_counter()
+    net = hyb.MLP(seed=2024)
     for it in range(train_steps):
-        idx = torch.randint(0, X.shape[0], (512,), device="cuda", generator=gen)
-        net.train_step(X[idx].contiguous(), T[idx].contiguous(), 2e-3)
+        idx = train[torch.randint(0, train.numel(), (batch,), device="cuda", generator=gen)]
+        net.train_step(X[idx].contiguous(), T[idx].contiguous(), lr)
     torch.cuda.synchronize()
-    train_s = time.perf_counter() - t0
+    train_s = time.perf_counter() - t1
+    Z = torch.empty(n_hold, hyb.MLP_OUT, device="cuda")
+    for a in range(0, n_hold, 4096):
+        sl = hold[a:a + 4096]
+        net.forward(X[sl].contiguous(), Z[a:a + len(sl)])
+    torch.cuda.synchronize()
+    gain_mix, gain_net = _heldout_gain(Z.cpu().numpy(), T[hold].cpu().numpy(), w.beta, eps)
+    del X, T, Z
     st = base.state()
     start = [([list(st["cre"][c, f, :st["k"][c, f]]) for f in range(F)],
-              [list(st["ann"][c, f, :st["k"][c, f]]) for f in range(F)]) for c in range(setup.n_chains)]
+              [list(st["ann"][c, f, :st["k"][c, f]]) for f in range(F)]) for c in range(C)]
     base.close()
-    out = {"workload": setup.name, "n_chains": setup.n_chains, "observable": "G(beta/2), flavor average",
-           "estimator": "across chains, spread of the chain means from their median absolute deviation "
-                        f"(plain variance and blocking with {n_blocks} blocks of {moves // n_blocks} moves "
-                        "reported beside it)",
-           "training": {"samples": int(X.shape[0]), "steps": train_steps, "batch": 512, "seconds": train_s},
-           "thermalisation": {"moves": therm, "mean_order": therm_order}, "eps": eps}
-    singles, runs = [], {}
+    out = {"workload": setup.name, "n_chains": C, "observable": "G(beta/2), flavor average, sign-weighted ratio",
+           "estimator": "jackknife over the independent chains of the pooled ratio; runs to a target error",
+           "target_se": target_se, "max_moves": max_moves, "chunk": chunk, "eps": eps,
+           "thermalisation": th,
+           "training": {"pairs": int(keep.sum().item()), "held_out": n_hold, "harvest_s": harvest_s,
+                        "steps": train_steps, "batch": batch, "lr": lr, "seconds": train_s,
+                        "heldout_gain_nats_per_pair": gain_mix, "heldout_gain_network_only": gain_net}}
+    runs, singles = {}, []
     for mode in ("uniform", "learned"):
         mc = mk(setup.seed + 1 + 100 * seed_offset)
         mc.set_configs(start)
         if mode == "learned":
             mc.attach_mlp(net, eps=eps)
-        for _ in range(snapshots):                    # single measurements (one move each)
+        for _ in range(4):                                  # single measurements (one move each)
             mc.reset_measurements()
             mc.sweep(1)
-            g1, _, nm1 = mc.accumulators()
-            singles.append(_sg_half(g1, nm1, w.beta, n_tau))
+            _, sgh, ms1, nm1 = _chain_sums(mc, w.beta, n_tau)
+            singles.append(sgh)
         mc.reset_measurements()
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        blocks, sg_tot, s_tot = _g_blocks(mc, w.beta, n_tau, n_blocks, moves)
-        dt = time.perf_counter() - t1
+        moves, wall, se = 0, 0.0, float("inf")
+        while moves < max_moves:
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            mc.sweep(chunk)
+            wall += time.perf_counter() - ta
+            moves += chunk
+            sgt, sgh, ms, nm = _chain_sums(mc, w.beta, n_tau)
+            g_half, se = _ratio_jackknife(sgh, ms)
+            print(f"[ess] {mode}: {moves} moves, {wall:.1f} s, G(beta/2) {float(g_half):.5f} +- {float(se):.5f}",
+                  file=sys.stderr, flush=True)
+            if se <= target_se:
+                break
+        G, Gse = _ratio_jackknife(sgt, ms)
         s2 = mc.stats()
-        runs[mode] = (blocks, dt, sg_tot, s_tot, s2)
+        means = sgh / np.maximum(nm, 1)
+        var_rob, n_out = _robust_var(means)
+        runs[mode] = {"moves": moves, "wall_s": wall, "reached": bool(se <= target_se), "g_half": float(g_half),
+                      "se": float(se), "time_to_target_s": wall * (float(se) / target_se) ** 2,
+                      "moves_to_target": moves * (float(se) / target_se) ** 2,
+                      "acceptance": (s2["insert_accepted"] + s2["remove_accepted"]) / max(1, s2["moves"]),
+                      "mean_order": s2["order_sum"] / max(1, s2["moves"]),
+                      "sign_avg": s2["sign_sum"] / max(1, s2["moves"]),
+                      "diagnostic_var_chain_means_plain": float(np.var(means, ddof=1)),
+                      "diagnostic_var_chain_means_mad": var_rob, "diagnostic_outlier_chains": n_out,
+                      "_G": G, "_Gse": Gse}
         mc.close()
     var1 = float(np.var(np.concatenate(singles), ddof=1))
-    for mode, (blocks, dt, sg_tot, s_tot, s2) in runs.items():
-        means = blocks.mean(axis=1)
-        ok = np.all(np.isfinite(blocks), axis=1)
-        var_block = float(np.mean(np.var(blocks[ok], axis=1, ddof=1)) / n_blocks)
-        var_cross = float(np.var(means[ok], ddof=1))
-        ess_b = float(ok.sum() * min(var1 / var_block, float(moves))) if var_block > 0 else float("nan")
-        ess_c = float(ok.sum() * min(var1 / var_cross, float(moves))) if var_cross > 0 else float("nan")
-        var_rob, n_out = _robust_var(means[ok])
-        ess_r = float(ok.sum() * min(var1 / var_rob, float(moves))) if var_rob > 0 else float("nan")
-        ess = ess_r
-        out[mode] = {"moves": moves, "wall_s": dt, "ess": ess, "ess_per_s": ess / dt,
-                     "ess_cross_chain": ess_c, "ess_blocking": ess_b,
-                     "ess_cross_chain_robust": ess_r, "ess_per_s_plain": ess_c / dt, "outlier_chains": n_out,
-                     "acceptance": (s2["insert_accepted"] + s2["remove_accepted"]) / max(1, s2["moves"]),
-                     "mean_order": s2["order_sum"] / max(1, s2["moves"]), "sign_avg": s2["sign_sum"] / max(1, s2["moves"]),
-                     "g_half": float(np.sum(sg_tot) / np.sum(s_tot))}
+    for mode, rr in runs.items():
+        rr["ess"] = var1 / rr["se"] ** 2
+        rr["ess_per_s"] = rr["ess"] / rr["wall_s"]
+    chi2, zmax = _two_sample(runs["uniform"]["_G"], runs["uniform"]["_Gse"], runs["learned"]["_G"],
+                             runs["learned"]["_Gse"])
+    for rr in runs.values():
+        rr.pop("_G")
+        rr.pop("_Gse")
+    out.update(runs)
     out["var_single"] = var1
-    # the spread of the chain means is taken from their median absolute deviation: with
-    # the plain variance a single outlying chain decided the ratio (4.4 against 0.7
-    # robust on one seed); the plain ratio is reported beside it
-    out["headline_estimator"] = "across chains, spread from the median absolute deviation"
-    out["learned_over_uniform_ess_per_s"] = out["learned"]["ess_per_s"] / out["uniform"]["ess_per_s"]
-    out["learned_over_uniform_ess_per_s_plain"] = out["learned"]["ess_per_s_plain"] / out["uniform"]["ess_per_s_plain"]
+    out["g_tau_two_sample"] = {"bins": n_tau, "chi2_per_bin": chi2, "max_abs_z": zmax}
+    out["learned_speedup_to_target"] = runs["uniform"]["time_to_target_s"] / runs["learned"]["time_to_target_s"]
     net.close()
     return out
 
@@ -552,7 +625,9 @@ def main():
     ap.add_argument("--spmm-only", action="store_true", help="only the block SpMM bandwidth benchmark")
     ap.add_argument("--no-ess", action="store_true", help="skip the learned vs uniform ESS measurement")
     ap.add_argument("--ess-only", action="store_true", help="only the learned vs uniform ESS measurement")
-    ap.add_argument("--ess-moves", type=int, default=20000, help="measured moves per sampler")
+    ap.add_argument("--ess-max-moves", type=int, default=12000, help="cap of measured moves per sampler")
+    ap.add_argument("--ess-target", type=float, default=1e-3, help="target standard error of G(beta/2)")
+    ap.add_argument("--ess-pairs", type=int, default=1_000_000, help="harvested training pairs")
     ap.add_argument("--ess-seed", type=int, default=0, help="offset of the chains' seeds")
     ap.add_argument("--ess-eps", type=float, default=0.1, help="uniform share of the learned insertion density")
     ap.add_argument("--no-seven", action="store_true", help="skip the 7-orbital mixed workload")
@@ -588,7 +663,9 @@ def main():
         print(json.dumps({"spmm_gated": measure_spmm(torch, hyb, I)}), flush=True)
         return
     if a.ess_only:
-        print(json.dumps({"ess": measure_ess(torch, hyb, I, moves=a.ess_moves, eps=a.ess_eps, seed_offset=a.ess_seed)}), flush=True)
+        print(json.dumps({"ess": measure_ess(torch, hyb, I, pairs=a.ess_pairs, target_se=a.ess_target,
+                                             max_moves=a.ess_max_moves, eps=a.ess_eps, seed_offset=a.ess_seed)}),
+              flush=True)
         return
     if a.comparator_only:
         print(json.dumps({"matrix_vs_krylov": measure_comparator(torch, hyb, I)}), flush=True)
@@ -647,7 +724,8 @@ def main():
     if not a.no_comparator:
         line["detail"]["matrix_vs_krylov"] = measure_comparator(torch, hyb, I)
     if not a.no_ess:
-        line["detail"]["ess"] = measure_ess(torch, hyb, I, moves=a.ess_moves, eps=a.ess_eps, seed_offset=a.ess_seed)
+        line["detail"]["ess"] = measure_ess(torch, hyb, I, pairs=a.ess_pairs, target_se=a.ess_target,
+                                            max_moves=a.ess_max_moves, eps=a.ess_eps, seed_offset=a.ess_seed)
     if not a.no_cpu:
         line["cpu_baseline"] = cpu_baseline(1, a.cpu_sample)
         if not a.no_seven:

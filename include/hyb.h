@@ -391,6 +391,45 @@ int hyb_mc_load(hyb_mc* mc, const void* buf, size_t len, void* stream);
  * uses a private stream of the default priority; calls on one hyb_mc must not overlap. */
 int hyb_mc_set_graphs(hyb_mc* mc, int32_t enable);
 
+/* ---- DMFT self-consistency on the Bethe lattice (Sec. V) -------------------------- */
+
+/* Replaces the Delta table of every chain (host [n_delta + 1], same grid) and rebuilds
+ * each chain's M_f = A_f^{-1}, log|det A_f| and the weight's sign from its times
+ * (Gauss-Jordan, FP64, on the device).  Measurements already accumulated are kept;
+ * callers normally reset them.  HYB_E_ARG for a non-finite table or when a chain's
+ * A_f becomes singular (the chain state is then unspecified until hyb_mc_set_configs). */
+int hyb_mc_set_delta(hyb_mc* mc, const double* delta, void* stream);
+
+/* The Bethe-lattice update for a semicircular density of states of half-bandwidth
+ * 2t: Delta_new(tau) = (1 - mix) Delta(tau) + mix t^2 G(tau), with G the measured
+ * G(tau) (hyb_mc_measure) averaged over the flavors (one Delta serves every flavor:
+ * paramagnetic, orbitally degenerate bath), with symmetrize & 1 also made
+ * particle-hole symmetric, G(tau) = G(beta - tau).  G is taken at the bin centres;
+ * its values at 0+ and beta- are extrapolated linearly from the two nearest bins and
+ * shifted together to satisfy G(0+) + G(beta-) = -1; the grid values of Delta come
+ * from linear interpolation.  delta_out: host [n_delta + 1].  HYB_E_STATE before any
+ * measurement. */
+int hyb_mc_bethe_delta(const hyb_mc* mc, double t, double mix, int32_t symmetrize, double* delta_out,
+                       void* stream);
+
+typedef struct {
+  double t;               /* Bethe-lattice hopping: Delta = t^2 G (bandwidth 4t) */
+  double mix;             /* linear mixing of the new Delta, (0, 1] */
+  int32_t n_iter;         /* self-consistency iterations */
+  int32_t therm_sweeps;   /* sweeps after each Delta update before measuring */
+  int32_t meas_sweeps;    /* measured sweeps per iteration */
+  int32_t symmetrize;     /* bit 0: particle-hole symmetric G */
+} hyb_dmft_params;
+
+/* n_iter DMFT iterations on the Bethe lattice: thermalise, reset and measure G(tau),
+ * record the flavor average of G at the two middle bins (g_half[it], host, may be
+ * NULL) and the average sign (sign_avg[it]), then hyb_mc_bethe_delta and
+ * hyb_mc_set_delta.  The final Delta is the chains' table (hyb_mc_get_delta). */
+int hyb_dmft_bethe(hyb_mc* mc, const hyb_dmft_params* p, double* g_half, double* sign_avg, void* stream);
+
+/* The chains' current Delta table (host out [n_delta + 1]). */
+int hyb_mc_get_delta(const hyb_mc* mc, double* delta);
+
 /* ---- learned insertion proposal ---------------------------------------------- */
 
 /* A 3-layer perceptron 352 -> 128 -> 128 -> 128 (ReLU between layers) mapping the

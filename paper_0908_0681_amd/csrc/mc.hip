@@ -827,6 +827,115 @@ int hyb_mc_load(hyb_mc* mc, const void* buf, size_t len, void* stream) {
   return HYB_OK;
 }
 
+int hyb_mc_set_delta(hyb_mc* mc, const double* delta, void* stream) {
+  if (!mc || !delta) return set_error(HYB_E_ARG, "NULL argument");
+  const int n = mc->p.n_delta;
+  for (int i = 0; i <= n; ++i)
+    if (!std::isfinite(delta[i])) return set_error(HYB_E_ARG, "non-finite Delta table entry %d", i);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  std::memcpy(const_cast<double*>(mc->p.delta), delta, sizeof(double) * (n + 1));
+  MC_HIP_TRY(hipMemcpyAsync(const_cast<double*>(mc->Q.delta), mc->p.delta, sizeof(double) * (n + 1),
+                            hipMemcpyHostToDevice, s));
+  // every chain's A_f changed: M_f, log|det| and the weight's sign from scratch
+  const int C = mc->p.n_chains;
+  const int32_t zero = 0;
+  MC_HIP_TRY(hipMemcpyAsync(mc->err, &zero, sizeof zero, hipMemcpyHostToDevice, s));
+  k_mc_rebuild<<<C * mc->F, 64, 0, s>>>(mc->Q, 0, 0, 1, mc->rb_ld, mc->rb_sd, mc->rb_drift_f, mc->err);
+  // the drift of this rebuild is the change of Delta, not an error of the updates:
+  // fold it into a scratch copy rather than the chains' drift record
+  double* scratch_drift = nullptr;
+  MC_HIP_TRY(hipMalloc(&scratch_drift, sizeof(double) * C));
+  MC_HIP_TRY(hipMemsetAsync(scratch_drift, 0, sizeof(double) * C, s));
+  k_mc_rebuild_finish<<<(C + 255) / 256, 256, 0, s>>>(mc->Q, 0, 0, 1, mc->rb_ld, mc->rb_sd, mc->rb_drift_f,
+                                                      scratch_drift, nullptr, nullptr);
+  int32_t err = 0;
+  const hipError_t e1 = hipMemcpyAsync(&err, mc->err, sizeof err, hipMemcpyDeviceToHost, s);
+  const hipError_t e2 = hipStreamSynchronize(s);
+  (void)hipFree(scratch_drift);
+  if (e1 != hipSuccess || e2 != hipSuccess) return set_error(HYB_E_HIP, "setting Delta failed");
+  if (err) {
+    MC_HIP_TRY(hipMemcpyAsync(mc->err, &zero, sizeof zero, hipMemcpyHostToDevice, s));
+    MC_HIP_TRY(hipStreamSynchronize(s));
+    return set_error(HYB_E_ARG, "a chain's hybridization matrix is singular with the new Delta");
+  }
+  return HYB_OK;
+}
+
+int hyb_mc_bethe_delta(const hyb_mc* mc, double t, double mix, int32_t symmetrize, double* delta_out, void* stream) {
+  if (!mc || !delta_out) return set_error(HYB_E_ARG, "NULL argument");
+  if (!(mix > 0.0 && mix <= 1.0) || !std::isfinite(t)) return set_error(HYB_E_ARG, "mix must be in (0, 1], t finite");
+  const int F = mc->F, NT = mc->p.n_tau, n = mc->p.n_delta;
+  if (NT < 2) return set_error(HYB_E_ARG, "the Bethe update needs at least 2 G(tau) bins");
+  std::vector<double> G(size_t(F) * NT);
+  double sgn = 0.0;
+  int rc = hyb_mc_measure(mc, G.data(), &sgn, stream);
+  if (rc) return rc;
+  // one Delta serves every flavor: average G over the flavors (paramagnetic,
+  // orbitally degenerate), then optionally G(tau) = G(beta - tau)
+  std::vector<double> g(NT, 0.0);
+  for (int b = 0; b < NT; ++b) {
+    for (int f = 0; f < F; ++f) g[b] += G[size_t(f) * NT + b];
+    g[b] /= F;
+  }
+  if (symmetrize & 1) {
+    std::vector<double> h(g);
+    for (int b = 0; b < NT; ++b) g[b] = 0.5 * (h[b] + h[NT - 1 - b]);
+  }
+  // bin centres (b + 1/2) beta / NT; the ends by linear extrapolation, shifted
+  // together so that G(0+) + G(beta-) = -1
+  const double beta = mc->p.beta, hb = beta / NT;
+  double g0 = g[0] - 0.5 * (g[1] - g[0]), gb = g[NT - 1] + 0.5 * (g[NT - 1] - g[NT - 2]);
+  const double shift = 0.5 * (-1.0 - g0 - gb);
+  g0 += shift;
+  gb += shift;
+  for (int k = 0; k <= n; ++k) {
+    const double tau = beta * k / n;
+    double gv;
+    const double x = tau / hb - 0.5;  // position in units of bins from the first centre
+    if (x <= 0.0) {
+      gv = g0 + (g[0] - g0) * (tau / (0.5 * hb));
+    } else if (x >= NT - 1) {
+      gv = g[NT - 1] + (gb - g[NT - 1]) * ((tau - (NT - 0.5) * hb) / (0.5 * hb));
+    } else {
+      const int b = int(x);
+      const double fr = x - b;
+      gv = g[b] + fr * (g[b + 1] - g[b]);
+    }
+    delta_out[k] = (1.0 - mix) * mc->p.delta[k] + mix * t * t * gv;
+  }
+  return HYB_OK;
+}
+
+int hyb_dmft_bethe(hyb_mc* mc, const hyb_dmft_params* p, double* g_half, double* sign_avg, void* stream) {
+  if (!mc || !p) return set_error(HYB_E_ARG, "NULL argument");
+  if (p->n_iter < 1 || p->therm_sweeps < 0 || p->meas_sweeps < 1)
+    return set_error(HYB_E_ARG, "n_iter and meas_sweeps must be >= 1, therm_sweeps >= 0");
+  const int F = mc->F, NT = mc->p.n_tau;
+  std::vector<double> G(size_t(F) * NT), d(mc->p.n_delta + 1);
+  for (int it = 0; it < p->n_iter; ++it) {
+    int rc = hyb_mc_sweep(mc, p->therm_sweeps, stream);
+    if (!rc) rc = hyb_mc_reset_measurements(mc, stream);
+    if (!rc) rc = hyb_mc_sweep(mc, p->meas_sweeps, stream);
+    double sg = 0.0;
+    if (!rc) rc = hyb_mc_measure(mc, G.data(), &sg, stream);
+    if (rc) return rc;
+    double gh = 0.0;
+    for (int f = 0; f < F; ++f) gh += 0.5 * (G[size_t(f) * NT + NT / 2 - 1] + G[size_t(f) * NT + NT / 2]);
+    if (g_half) g_half[it] = gh / F;
+    if (sign_avg) sign_avg[it] = sg;
+    rc = hyb_mc_bethe_delta(mc, p->t, p->mix, p->symmetrize, d.data(), stream);
+    if (!rc) rc = hyb_mc_set_delta(mc, d.data(), stream);
+    if (rc) return rc;
+  }
+  return HYB_OK;
+}
+
+int hyb_mc_get_delta(const hyb_mc* mc, double* delta) {
+  if (!mc || !delta) return set_error(HYB_E_ARG, "NULL argument");
+  std::memcpy(delta, mc->p.delta, sizeof(double) * (mc->p.n_delta + 1));
+  return HYB_OK;
+}
+
 int hyb_mc_step_count(const hyb_mc* mc, int64_t* step) {
   if (!mc || !step) return set_error(HYB_E_ARG, "NULL argument");
   *step = mc->step;

@@ -66,6 +66,11 @@ class McStatsC(C.Structure):
                 ("order_sum", C.c_double), ("sign_sum", C.c_double), ("max_drift", C.c_double)]
 
 
+class DmftParamsC(C.Structure):
+    _fields_ = [("t", C.c_double), ("mix", C.c_double), ("n_iter", C.c_int32), ("therm_sweeps", C.c_int32),
+                ("meas_sweeps", C.c_int32), ("symmetrize", C.c_int32)]
+
+
 # name -> (restype, argtypes)
 _P = C.c_void_p
 _SIGS = {
@@ -109,6 +114,10 @@ _SIGS = {
     "hyb_mc_step_count": (C.c_int, [_P, _P]),
     "hyb_mc_set_graphs": (C.c_int, [_P, C.c_int32]),
     "hyb_mc_save": (C.c_int, [_P, _P, C.POINTER(C.c_size_t), _P]),
+    "hyb_mc_set_delta": (C.c_int, [_P, _P, _P]),
+    "hyb_mc_get_delta": (C.c_int, [_P, _P]),
+    "hyb_mc_bethe_delta": (C.c_int, [_P, C.c_double, C.c_double, C.c_int32, _P, _P]),
+    "hyb_dmft_bethe": (C.c_int, [_P, C.POINTER(DmftParamsC), _P, _P, _P]),
     "hyb_mc_load": (C.c_int, [_P, _P, C.c_size_t, _P]),
     "hyb_mc_attach_mlp": (C.c_int, [_P, _P, C.c_double]),
     "hyb_mc_harvest": (C.c_int, [_P, C.c_int64, _P, _P, _P]),
@@ -513,6 +522,35 @@ class MC:
         """Restores a checkpoint written by save() (hyb_mc_load)."""
         buf = C.create_string_buffer(blob, len(blob))
         _check(lib().hyb_mc_load(self.h, buf, len(blob), _stream(stream)))
+
+    def set_delta(self, delta, stream=None):
+        """Replaces the Delta table (same grid); M, log|det| and signs rebuilt per chain."""
+        d = np.ascontiguousarray(delta, dtype=np.float64)
+        if d.shape != self.delta.shape:
+            raise ValueError(f"Delta table of {d.shape}, the chains use {self.delta.shape}")
+        _check(lib().hyb_mc_set_delta(self.h, _ptr(d), _stream(stream)))
+        self.delta = d
+
+    def get_delta(self):
+        d = np.zeros_like(self.delta)
+        _check(lib().hyb_mc_get_delta(self.h, _ptr(d)))
+        return d
+
+    def bethe_delta(self, t=1.0, mix=1.0, symmetrize=True, stream=None):
+        """Delta_new = (1 - mix) Delta + mix t^2 G from the current measurements."""
+        d = np.zeros_like(self.delta)
+        _check(lib().hyb_mc_bethe_delta(self.h, float(t), float(mix), 1 if symmetrize else 0, _ptr(d),
+                                        _stream(stream)))
+        return d
+
+    def dmft_bethe(self, n_iter, therm_sweeps, meas_sweeps, t=1.0, mix=1.0, symmetrize=True, stream=None):
+        """hyb_dmft_bethe: returns (G(beta/2) per iteration, <sign> per iteration)."""
+        p = DmftParamsC(float(t), float(mix), int(n_iter), int(therm_sweeps), int(meas_sweeps),
+                        1 if symmetrize else 0)
+        gh, sa = np.zeros(n_iter), np.zeros(n_iter)
+        _check(lib().hyb_dmft_bethe(self.h, C.byref(p), _ptr(gh), _ptr(sa), _stream(stream)))
+        self.delta = self.get_delta()
+        return gh, sa
 
     def set_graphs(self, enable=True):
         """Replay each sweep from a captured HIP graph (same chains bit for bit)."""

@@ -287,6 +287,17 @@ def mc_setup(k: int = 3, n_chains: int | None = None) -> McSetup:
     raise ValueError(k)
 
 
+def dmft_setup(n_orb: int, U: float, beta: float, n_chains: int = 128, n_delta: int = 1000) -> McSetup:
+    """The Bethe-lattice DMFT models of Sec. V: n_orb degenerate orbitals, J = U/6,
+    half filling (mu_half), every local state kept (full trace), chains starting
+    empty, the initial bath the non-interacting semicircle (D = 2, t = 1)."""
+    J = U / 6.0
+    p = kanamori(n_orb, U=U, J=J, mu=mu_half(n_orb, U, J))
+    w = Workload(f"kanamori-{n_orb}orb-U{U:g}-b{beta:g}", p, beta, 0, 0.0, 0, "fp64", -1.0)
+    return McSetup(f"{w.name}-dmft", w, n_chains, n_delta, semicircle_delta(beta, n_delta), 3100 + n_orb, 0, 48,
+                   17 + n_orb)
+
+
 def mc_initial_configs(setup: McSetup):
     """Per chain: (cre, ann) with cre[f] / ann[f] the creator / annihilator times of
     flavor f in label order (the i-th creator in time is paired with the i-th

@@ -56,3 +56,49 @@ def test_robust_variance_ignores_outlying_chains():
     v2, n2 = bench._robust_var(y)
     assert v2 == pytest.approx(v, rel=0.01) and n2 == 3
     assert np.var(y) > 50 * v2
+
+
+def test_ratio_jackknife_matches_leave_one_out():
+    rng = np.random.default_rng(5)
+    C = 40
+    s = rng.integers(50, 100, C).astype(float)
+    sg = rng.normal(size=C) * 3.0 + 0.5 * s
+    R, se = bench._ratio_jackknife(sg, s)
+    assert R == pytest.approx(sg.sum() / s.sum(), rel=1e-14)
+    loo = np.array([(sg.sum() - sg[c]) / (s.sum() - s[c]) for c in range(C)])
+    want = np.sqrt((C - 1) / C * np.sum((loo - loo.mean()) ** 2))
+    assert se == pytest.approx(want, rel=1e-12)
+    # equal weights: the jackknife error of a mean is the plain standard error
+    x = rng.normal(size=C)
+    _, se2 = bench._ratio_jackknife(x, np.ones(C))
+    assert se2 == pytest.approx(np.std(x, ddof=1) / np.sqrt(C), rel=1e-12)
+    # per-bin curves at once
+    sgk = np.stack([sg, 2 * sg], axis=1)
+    Rk, sek = bench._ratio_jackknife(sgk, s)
+    assert np.allclose(Rk, [R, 2 * R]) and np.allclose(sek, [se, 2 * se])
+
+
+def test_drift_and_two_sample_statistics():
+    rng = np.random.default_rng(6)
+    a = rng.normal(size=400)
+    assert abs(bench._drift_t(a, a + rng.normal(size=400) * 0.1)) < 4.0
+    assert bench._drift_t(a, a + 1.0 + rng.normal(size=400) * 0.1) > 50.0
+    chi2, zmax = bench._two_sample([1.0, 2.0], [0.1, 0.1], [1.0, 2.0], [0.1, 0.1])
+    assert chi2 == 0.0 and zmax == 0.0
+    chi2, zmax = bench._two_sample([1.0], [0.3], [0.0], [0.4])
+    assert zmax == pytest.approx(2.0) and chi2 == pytest.approx(4.0)
+
+
+def test_heldout_gain_of_flat_and_sharp_networks():
+    N = 1000
+    rng = np.random.default_rng(7)
+    t = np.stack([rng.integers(0, 64, N), rng.integers(0, 64, N)], axis=1)
+    mix, net = bench._heldout_gain(np.zeros((N, 128)), t, 50.0, 0.1)
+    assert mix == pytest.approx(0.0, abs=1e-12) and net == pytest.approx(0.0, abs=1e-12)
+    # a network certain of the right bins: network gain 2 log 64, mixture log(0.9*64^2 + 0.1)
+    z = np.full((N, 128), -1e3)
+    z[np.arange(N), t[:, 0]] = 0.0
+    z[np.arange(N), 64 + t[:, 1]] = 0.0
+    mix, net = bench._heldout_gain(z, t, 50.0, 0.1)
+    assert net == pytest.approx(2 * np.log(64))
+    assert mix == pytest.approx(np.log(0.9 * 64 ** 2 + 0.1))
