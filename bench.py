@@ -245,6 +245,85 @@ def measure_comparator(torch, hyb, I, orbitals=(2, 3, 4, 5, 6, 7), n_configs=512
     return rows
 
 
+def _mc_run(hyb, I, params, window, beta, n_chains, therm, meas, n_tau, seed, precision="fp64"):
+    """Chains from empty configurations on the semicircular bath: therm moves, then meas
+    measured moves; returns G(tau) and the sector weights at beta/2 with their
+    jackknife-over-chains errors, and the run's statistics."""
+    import numpy as np
+    m = hyb.Model(params, precision=precision, retain_window=window)
+    delta = I.semicircle_delta(beta, 1000)
+    mc = hyb.MC(m, n_chains, beta, delta, kmax=60, nmax_ops=1024, seed=seed, n_tau=n_tau)
+    t0 = time.perf_counter()
+    mc.sweep(therm)
+    mc.reset_measurements()
+    mc.sweep(meas)
+    wall = time.perf_counter() - t0
+    sgt, _, ms, _ = _chain_sums(mc, beta, n_tau)
+    G, Gse = _ratio_jackknife(sgt, ms)
+    _, sec = mc.sector_weights()
+    P, Pse = _ratio_jackknife(sec, ms)
+    st = mc.stats()
+    info = m.info()
+    mc.close()
+    return {"G": G, "G_se": Gse, "P": P, "P_se": Pse, "n_retained": info["n_retained"], "wall_s": wall,
+            "mean_order": st["order_sum"] / max(1, st["moves"]), "sign_avg": st["sign_sum"] / max(1, st["moves"]),
+            "acceptance": (st["insert_accepted"] + st["remove_accepted"]) / max(1, st["moves"])}
+
+
+def measure_truncation_study(torch, hyb, I, n_chains=256, n_tau=40):
+    """Sec. IV.A (Fig. 1) and Sec. IV.C (Fig. 4) on the GPU.
+    (A) 3 orbitals, U = 6, J = U/6, half filling (mu = 5U/2 - 5J), no crystal field,
+        semicircular bath: G(tau) with the trace truncated to the ground quartet
+        (N_tr = 4) against the full trace, beta = 3.125 ... 50.
+    (B) 5 orbitals, U = 6, J = U/6, beta = 50, mu - mu_half = 4.98, 5.00, 5.02 (ground
+        multiplets of 6, 6 + 25 and 25 states): the weights of the (n_up, n_dn) sectors
+        at beta/2, compared between the three truncations.
+    Errors: jackknife over independent chains."""
+    import numpy as np
+    out = {"fig1_three_orbital": [], "fig4_five_orbital": {}}
+    U, J = 6.0, 1.0
+    p3 = I.kanamori(3, U=U, J=J, mu=2.5 * U - 5 * J)
+    for beta in (3.125, 6.25, 12.5, 25.0, 50.0):
+        tr = _mc_run(hyb, I, p3, 1e-5, beta, n_chains, 2000, 8000, n_tau, 41)
+        full = _mc_run(hyb, I, p3, -1.0, beta, n_chains, 2000, 8000, n_tau, 43)
+        d = tr["G"] - full["G"]
+        z = d / np.sqrt(tr["G_se"] ** 2 + full["G_se"] ** 2)
+        row = {"beta": beta, "n_tr": tr["n_retained"], "n_full": full["n_retained"],
+               "max_abs_dG": float(np.max(np.abs(d))), "G_half_truncated": float(tr["G"][n_tau // 2]),
+               "G_half_full": float(full["G"][n_tau // 2]), "chi2_per_bin": float(np.mean(z ** 2)),
+               "max_abs_z": float(np.max(np.abs(z))), "mean_order_full": full["mean_order"],
+               "seconds": tr["wall_s"] + full["wall_s"]}
+        print(f"[truncation] 3 orbitals beta {beta}: max |dG| {row['max_abs_dG']:.4f}, chi2/bin "
+              f"{row['chi2_per_bin']:.2f}", file=sys.stderr, flush=True)
+        out["fig1_three_orbital"].append(row)
+    mh = I.mu_half(5, U, J)
+    runs = {}
+    for dmu in (4.98, 5.0, 5.02):
+        p5 = I.kanamori(5, U=U, J=J, mu=mh + dmu)
+        runs[dmu] = _mc_run(hyb, I, p5, 1e-5, 50.0, n_chains, 5000, 5000, n_tau, 53)
+        print(f"[truncation] 5 orbitals mu_half + {dmu}: N_tr {runs[dmu]['n_retained']}, "
+              f"{runs[dmu]['wall_s']:.0f} s", file=sys.stderr, flush=True)
+    for dmu, rr in runs.items():
+        top = np.argsort(rr["P"])[::-1][:6]
+        out["fig4_five_orbital"][f"{dmu:.2f}"] = {
+            "n_tr": rr["n_retained"], "weights": [float(x) for x in rr["P"]], "errors": [float(x) for x in rr["P_se"]],
+            "largest": {f"({int(b) % 6},{int(b) // 6})": round(float(rr["P"][b]), 4) for b in top},
+            "mean_order": rr["mean_order"], "sign_avg": rr["sign_avg"], "seconds": rr["wall_s"]}
+    keys = sorted(runs)
+    cmp = {}
+    for i in range(len(keys)):
+        for j in range(i + 1, len(keys)):
+            a, b = runs[keys[i]], runs[keys[j]]
+            sig = np.sqrt(a["P_se"] ** 2 + b["P_se"] ** 2)
+            ok = sig > 0
+            z = (a["P"] - b["P"])[ok] / sig[ok]
+            cmp[f"{keys[i]:.2f} vs {keys[j]:.2f}"] = {"max_abs_dP": float(np.max(np.abs(a["P"] - b["P"]))),
+                                                   "chi2_per_sector": float(np.mean(z ** 2)),
+                                                   "max_abs_z": float(np.max(np.abs(z)))}
+    out["fig4_comparison"] = cmp
+    return out
+
+
 def measure_spmm(torch, hyb, I, n_vec=262144, reps=10):
     """Gated bandwidth benchmark: Y = (H_b - c_b) X on the 7-orbital (n_up, n_dn) =
     (3, 4) block (1225 states, 8400 off-diagonal entries), FP32, 16-vector panels.
@@ -633,6 +712,8 @@ def main():
     ap.add_argument("--no-seven", action="store_true", help="skip the 7-orbital mixed workload")
     ap.add_argument("--no-comparator", action="store_true", help="skip the Krylov vs matrix comparison")
     ap.add_argument("--comparator-only", action="store_true", help="only the Krylov vs matrix comparison")
+    ap.add_argument("--truncation-study", action="store_true",
+                    help="only the truncation study (3-orbital G(tau) N_tr = 4 vs full; 5-orbital sectors at beta/2)")
     ap.add_argument("--seven-only", action="store_true", help="only the 7-orbital mixed workload (profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (3 times) and exit: the reference "
@@ -666,6 +747,9 @@ def main():
         print(json.dumps({"ess": measure_ess(torch, hyb, I, pairs=a.ess_pairs, target_se=a.ess_target,
                                              max_moves=a.ess_max_moves, eps=a.ess_eps, seed_offset=a.ess_seed)}),
               flush=True)
+        return
+    if a.truncation_study:
+        print(json.dumps({"truncation_study": measure_truncation_study(torch, hyb, I)}), flush=True)
         return
     if a.comparator_only:
         print(json.dumps({"matrix_vs_krylov": measure_comparator(torch, hyb, I)}), flush=True)

@@ -361,13 +361,24 @@ int hyb_mc_measure(const hyb_mc* mc, double* G, double* sign_avg, void* stream);
 int hyb_mc_reset_measurements(hyb_mc* mc, void* stream);
 int hyb_mc_step_count(const hyb_mc* mc, int64_t* step);
 
+/* Weights of the (n_up, n_dn) sectors at tau = beta/2 (Sec. IV.C, Fig. 4; Sec. III
+ * measures at beta/2): for a configuration, P_s = sum_{r: path r in sector s at
+ * beta/2} t_r / sum_r t_r over the retained-state paths of its trace (the blocks are
+ * conserved between operators, so each path's sector at beta/2 follows from its
+ * operators alone); accumulated with sign(w) at every measurement.
+ * w (host [n_blocks], may be NULL): sum over chains of the accumulators / sum of
+ * signs, indexed by block = n_dn (n_orb + 1) + n_up.  acc (host [n_chains][n_blocks],
+ * may be NULL): the raw per-chain accumulators (for error analysis).  Reset by
+ * hyb_mc_reset_measurements; part of the checkpoint. */
+int hyb_mc_sector_weights(const hyb_mc* mc, double* w, double* acc, void* stream);
+
 /* Checkpoint of every chain (the checkpoint/resume of a long run): pair lists, M,
  * the time-ordered operator lists and weight factors, the move counter (which
  * keys the Philox counters, so the random stream resumes where it stopped), the
  * statistics and the G(tau) accumulators.  hyb_mc_save with buf = NULL writes the
  * size needed to *len; otherwise *len is the buffer size on entry and the bytes
  * written on return (HYB_E_ARG if too small).  The blob is host memory owned by
- * the caller; its layout is a fixed header (magic "HYBMCCK1", sizes, beta, seed,
+ * the caller; its layout is a fixed header (magic "HYBMCCK2", sizes, beta, seed,
  * move counter, a hash of the Delta table) followed by the raw arrays.
  * hyb_mc_load restores a checkpoint into chains created with the same sizes, beta,
  * seed, Delta table and model precision (else HYB_E_ARG).  It then checks the

@@ -252,6 +252,13 @@ class Chain:
             return kind, True
         return kind, False
 
+    def measure_sectors(self, acc: np.ndarray):
+        """Adds sign(w) * P_s(beta/2) of the current configuration into acc[s]
+        (TraceOracle.sector_weights)."""
+        tau, fl, dg = merged(self.cre, self.ann)
+        for b, p in self.tr.sector_weights(tau, fl, dg, self.beta, 0.5 * self.beta).items():
+            acc[b] += self.sign * p
+
     def measure(self, acc: np.ndarray):
         """Adds sign(w) * sum_ij M[j][i] (signed, binned) into acc[f][bin]."""
         F, n_tau = acc.shape

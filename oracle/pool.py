@@ -111,6 +111,7 @@ def _chain_run(task):
         ch = MC.Chain(_W["oracle"], _W["table"], _W["beta"], [[]] * F, [[]] * F, _W["kmax"])
     start = ([list(x) for x in ch.cre], [list(x) for x in ch.ann], ch.sign, ch.logw)
     acc = np.zeros((F, n_tau))
+    sec = np.zeros(len(_W["oracle"].spec.states))
     accepted, margins = 0, []
     for step in range(n_moves):
         kind, a = ch.step(MC.move_uniforms(seed, c, step))
@@ -119,7 +120,8 @@ def _chain_run(task):
             margins.append(ch.last_margin)
         if (step + 1) % meas_every == 0:
             ch.measure(acc)
-    return dict(chain=c, start=start, cre=ch.cre, ann=ch.ann, sign=ch.sign, logw=ch.logw, acc=acc,
+            ch.measure_sectors(sec)
+    return dict(chain=c, start=start, cre=ch.cre, ann=ch.ann, sign=ch.sign, logw=ch.logw, acc=acc, sec=sec,
                 accepted=accepted, min_margin=min(margins) if margins else np.inf)
 
 

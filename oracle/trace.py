@@ -167,6 +167,32 @@ class TraceOracle:
             return True, 0, -np.inf
         return True, (1 if ov > 0 else -1), ell + np.log(abs(ov)) - beta * E0
 
+    # -- sector weights at a time inside the interval ---------------------------
+    def sector_weights(self, tau, flavor, dagger, beta: float, tau_m: float):
+        """Weights of the (n_up, n_dn) sectors at time tau_m (Sec. IV.C, Fig. 4):
+        P_s = sum_{i: path i in block s at tau_m} t_i / sum_i t_i, with t_i the
+        retained-state contributions of path(); the block of path i at tau_m is the
+        block reached after the operators earlier than tau_m (H conserves the blocks
+        in between).  Returns a dict block -> weight (empty for a zero trace)."""
+        out, tot, ts = {}, 0.0, []
+        for r in range(len(self.R.block)):
+            feas, sg, lg = self.path(tau, flavor, dagger, beta, r)
+            if not feas or sg == 0:
+                continue
+            b = int(self.R.block[r])
+            for k in range(len(tau)):
+                if tau[k] < tau_m:
+                    b = self.target_block(b, int(flavor[k]), int(dagger[k]))
+            ts.append((b, sg, lg))
+        if not ts:
+            return out
+        m = max(lg for _, _, lg in ts)
+        for b, sg, lg in ts:
+            t = sg * np.exp(lg - m)
+            out[b] = out.get(b, 0.0) + t
+            tot += t
+        return {b: v / tot for b, v in out.items()}
+
     # -- conditioning ----------------------------------------------------------
     def path_condition(self, tau, flavor, dagger, r: int):
         """Cut-point condition numbers kappa_k = 1 / |<L_k|R_k>| of one path.

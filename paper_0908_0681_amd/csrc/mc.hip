@@ -51,6 +51,13 @@ __global__ __launch_bounds__(64) void k_mc_accept(MCParams Q, int64_t off, int32
   mc_accept(Q, blockIdx.x, step, ((step + 1) % meas_every) == 0 ? 1 : 0, canon);
 }
 
+__global__ __launch_bounds__(64) void k_mc_sectors(MCParams Q) { mc_sectors(Q, blockIdx.x); }
+
+__global__ void k_mc_copy(const double* src, double* dst, int64_t n) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+
 __global__ __launch_bounds__(64) void k_mc_choose(MCParams Q, int64_t off) {
   mc_choose(Q, blockIdx.x, *Q.step_dev + off);
 }
@@ -206,6 +213,7 @@ int launch_moves(hyb_mc* mc, int64_t moves, hipStream_t s) {
     k_mc_propose<<<C, 64, 0, s>>>(mc->Q, mv);
     int rc = run_traces(mc, s);
     if (rc) return rc;
+    k_mc_sectors<<<C, 64, 0, s>>>(mc->Q);
     k_mc_accept<<<C, 64, smem, s>>>(mc->Q, mv, mc->p.meas_every);
     if (mc->p.rebuild_every > 0) {
       const int32_t every = mc->p.rebuild_every, apply = 1;
@@ -276,7 +284,7 @@ int capture_sweep(hyb_mc* mc) {
 // ---- checkpoints ------------------------------------------------------------------
 
 struct CkptHeader {
-  char magic[8];  // "HYBMCCK1"
+  char magic[8];  // "HYBMCCK2"
   int32_t n_chains, F, kmax, nmax_ops, n_tau, n_delta, meas_every, moves_per_sweep, rebuild_every, precision;
   double beta;
   uint64_t seed;
@@ -284,7 +292,7 @@ struct CkptHeader {
   uint64_t delta_hash;  // FNV-1a over the bytes of the Delta table
   uint64_t payload;     // bytes after the header
 };
-constexpr char kCkptMagic[8] = {'H', 'Y', 'B', 'M', 'C', 'C', 'K', '1'};
+constexpr char kCkptMagic[8] = {'H', 'Y', 'B', 'M', 'C', 'C', 'K', '2'};
 
 uint64_t fnv1a(const void* p, size_t n) {
   const unsigned char* b = static_cast<const unsigned char*>(p);
@@ -312,7 +320,8 @@ std::vector<CkptField> ckpt_fields(const hyb_mc* mc) {
           {Q.cur_signtr, C * 4},      {Q.cur_logdet, C * 8},     {Q.cur_signdet, C * 4},
           {Q.cur_sign, C * 4},        {Q.stats, C * ST_N * 8},   {Q.sign_sum, C * 8},
           {Q.gacc, C * F * NT * 8},   {Q.meas_sign, C * 8},      {Q.n_meas, C * 8},
-          {mc->drift, C * 8}};
+          {mc->drift, C * 8},         {Q.cur_psec, C * size_t(Q.n_blocks) * 8},
+          {Q.sec_acc, C * size_t(Q.n_blocks) * 8}};
 }
 
 CkptHeader ckpt_header(const hyb_mc* mc) {
@@ -406,11 +415,22 @@ int hyb_mc_create(hyb_model* m, const hyb_mc_params* p, hyb_mc** out) {
       (rc = mc_alloc(mc, Q.gacc, size_t(C) * F * p->n_tau)) || (rc = mc_alloc(mc, Q.meas_sign, C)) ||
       (rc = mc_alloc(mc, Q.n_meas, C)) || (rc = mc_alloc(mc, mc->err, 1)) || (rc = mc_alloc(mc, Q.step_dev, 1)) ||
       (rc = mc_alloc(mc, mc->rb_ld, size_t(C) * F)) || (rc = mc_alloc(mc, mc->rb_sd, size_t(C) * F)) ||
-      (rc = mc_alloc(mc, mc->rb_drift_f, size_t(C) * F)) || (rc = mc_alloc(mc, mc->drift, C)))
+      (rc = mc_alloc(mc, mc->rb_drift_f, size_t(C) * F)) || (rc = mc_alloc(mc, mc->drift, C)) ||
+      (rc = mc_alloc(mc, Q.psec_prop, size_t(C) * m->n_blocks)) ||
+      (rc = mc_alloc(mc, Q.cur_psec, size_t(C) * m->n_blocks)) ||
+      (rc = mc_alloc(mc, Q.sec_acc, size_t(C) * m->n_blocks)))
     return fail(rc);
   char* ws = nullptr;
   if ((rc = mc_alloc(mc, ws, trace_ws_bytes(m, C)))) return fail(rc);
   mc->trace_ws = ws;
+  {
+    const ResidentPairs pr = trace_resident_pairs(m, C, ws);
+    Q.pr_sign = pr.sign;
+    Q.pr_log = pr.log;
+    Q.pr_mid = pr.midblk;
+    Q.n_blocks = m->n_blocks;
+    Q.n_ret = int32_t(m->ret_block.size());
+  }
   Q.delta = d_delta;
   Q.p_begin = d_begin;
   Q.t_log = mc->t_log;
@@ -523,9 +543,16 @@ int hyb_mc_set_configs(hyb_mc* mc, const int32_t* k, const double* cre, const do
   MC_HIP_TRY(hipMemcpyAsync(mc->drift, zerosd.data(), sizeof(double) * C, hipMemcpyHostToDevice, s));
   // a new state starts without the error of an earlier failed sweep
   MC_HIP_TRY(hipMemcpyAsync(mc->err, zeros64.data(), sizeof(int32_t), hipMemcpyHostToDevice, s));
-  // traces of the initial configurations (through the proposal slots)
+  // traces of the initial configurations (through the proposal slots) and their
+  // sector distributions at beta/2
   int rc = run_traces(mc, s);
   if (rc) return rc;
+  {
+    const int64_t nsec = int64_t(C) * mc->m->n_blocks;
+    k_mc_sectors<<<C, 64, 0, s>>>(Q);
+    k_mc_copy<<<unsigned((nsec + 255) / 256), 256, 0, s>>>(Q.psec_prop, Q.cur_psec, nsec);
+    MC_HIP_TRY(hipMemsetAsync(Q.sec_acc, 0, sizeof(double) * nsec, s));
+  }
   std::vector<double> tl(C);
   std::vector<int8_t> ts(C);
   int32_t err = 0;
@@ -680,6 +707,7 @@ int hyb_mc_reset_measurements(hyb_mc* mc, void* stream) {
   MC_HIP_TRY(hipMemsetAsync(mc->Q.n_meas, 0, sizeof(int64_t) * C, s));
   MC_HIP_TRY(hipMemsetAsync(mc->Q.stats, 0, sizeof(int64_t) * size_t(C) * ST_N, s));
   MC_HIP_TRY(hipMemsetAsync(mc->Q.sign_sum, 0, sizeof(double) * C, s));
+  MC_HIP_TRY(hipMemsetAsync(mc->Q.sec_acc, 0, sizeof(double) * size_t(C) * mc->m->n_blocks, s));
   MC_HIP_TRY(hipStreamSynchronize(s));
   return HYB_OK;
 }
@@ -933,6 +961,28 @@ int hyb_dmft_bethe(hyb_mc* mc, const hyb_dmft_params* p, double* g_half, double*
 int hyb_mc_get_delta(const hyb_mc* mc, double* delta) {
   if (!mc || !delta) return set_error(HYB_E_ARG, "NULL argument");
   std::memcpy(delta, mc->p.delta, sizeof(double) * (mc->p.n_delta + 1));
+  return HYB_OK;
+}
+
+int hyb_mc_sector_weights(const hyb_mc* mc, double* w, double* acc, void* stream) {
+  if (!mc || (!w && !acc)) return set_error(HYB_E_ARG, "NULL argument");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const int C = mc->p.n_chains, NB = mc->m->n_blocks;
+  std::vector<double> a(size_t(C) * NB), ms(C);
+  MC_HIP_TRY(hipMemcpyAsync(a.data(), mc->Q.sec_acc, sizeof(double) * a.size(), hipMemcpyDeviceToHost, s));
+  MC_HIP_TRY(hipMemcpyAsync(ms.data(), mc->Q.meas_sign, sizeof(double) * C, hipMemcpyDeviceToHost, s));
+  MC_HIP_TRY(hipStreamSynchronize(s));
+  if (acc) std::memcpy(acc, a.data(), sizeof(double) * a.size());
+  if (w) {
+    double ssum = 0.0;
+    for (int c = 0; c < C; ++c) ssum += ms[c];
+    if (ssum == 0.0) return set_error(HYB_E_STATE, "no measurements (or zero average sign)");
+    for (int b = 0; b < NB; ++b) {
+      double t = 0.0;
+      for (int c = 0; c < C; ++c) t += a[size_t(c) * NB + b];
+      w[b] = t / ssum;
+    }
+  }
   return HYB_OK;
 }
 

@@ -69,7 +69,43 @@ struct MCParams {
   double eps_mix;
   __bf16* X;
   const float* logits;
+  // (n_up, n_dn) sector weights at beta/2: the trace workspace's per-path results of
+  // the proposals (sign, log, block at beta/2; pair id = chain * n_ret + r), the
+  // proposal's distribution over the n_blocks sectors, the current one, and the
+  // sign-weighted accumulators, each [C][n_blocks]
+  int32_t n_blocks, n_ret;
+  const int8_t* pr_sign;
+  const double* pr_log;
+  const int32_t* pr_mid;
+  double* psec_prop;
+  double* cur_psec;
+  double* sec_acc;
 };
+
+// The proposal's sector distribution at beta/2 (lane 0 of the chain's wavefront, in
+// retained-state order so that repeated runs are bitwise equal):
+// P_s = sum_{r: block_r(beta/2) = s} t_r / sum_r t_r over the retained-state paths.
+__device__ inline void mc_sectors(const MCParams& Q, int c) {
+  if (threadIdx.x != 0) return;
+  const int64_t base = int64_t(c) * Q.n_ret;
+  double mx = -INFINITY;
+  for (int r = 0; r < Q.n_ret; ++r)
+    if (Q.pr_sign[base + r] != 0) mx = fmax(mx, Q.pr_log[base + r]);
+  double* out = Q.psec_prop + int64_t(c) * Q.n_blocks;
+  for (int b = 0; b < Q.n_blocks; ++b) out[b] = 0.0;
+  if (!(mx > -INFINITY)) return;
+  double tot = 0.0;
+  for (int r = 0; r < Q.n_ret; ++r) {
+    const int8_t sg = Q.pr_sign[base + r];
+    const int b = Q.pr_mid[base + r];
+    if (sg == 0 || b < 0) continue;
+    const double t = sg * exp(Q.pr_log[base + r] - mx);
+    out[b] += t;
+    tot += t;
+  }
+  if (tot != 0.0)
+    for (int b = 0; b < Q.n_blocks; ++b) out[b] /= tot;
+}
 
 // ---- generator -------------------------------------------------------------
 
@@ -454,6 +490,8 @@ __device__ inline void mc_accept(const MCParams& Q, int c, int64_t step, int mea
     }
     __syncthreads();
     const int sp = perm_sign(Q, c, canon);
+    for (int b = lane; b < Q.n_blocks; b += 64)
+      Q.cur_psec[int64_t(c) * Q.n_blocks + b] = Q.psec_prop[int64_t(c) * Q.n_blocks + b];
     if (lane == 0) {
       Q.cur_n[c] = n_new;
       Q.cur_logtr[c] = Q.t_log[c];
@@ -493,6 +531,8 @@ __device__ inline void mc_accept(const MCParams& Q, int c, int64_t step, int mea
         atomicAdd(&acc[b], sgn * s * Mg[j * KM + i]);
       }
     }
+    for (int b = lane; b < Q.n_blocks; b += 64)
+      Q.sec_acc[int64_t(c) * Q.n_blocks + b] += sgn * Q.cur_psec[int64_t(c) * Q.n_blocks + b];
     if (lane == 0) {
       Q.meas_sign[c] += sgn;
       Q.n_meas[c] += 1;

@@ -320,7 +320,8 @@ static int error_from_bits(int bits) {
 
 namespace {
 struct ResidentLayout {
-  size_t cnt, work, psign, plog, psteps, psub, prs, prw, srs, srw, sblock, sstatus, ssteps, ssubs, sell, svec, total;
+  size_t cnt, work, psign, plog, psteps, psub, prs, prw, srs, srw, sblock, sstatus, ssteps, ssubs, sell, midblk, svec,
+      total;
 };
 ResidentLayout resident_layout(const hyb_model* m, int nc, size_t vbytes) {
   const int64_t npairs = int64_t(nc) * int64_t(m->ret_block.size());
@@ -347,6 +348,7 @@ ResidentLayout resident_layout(const hyb_model* m, int nc, size_t vbytes) {
   L.ssteps = take(npairs * sizeof(int32_t));
   L.ssubs = take(npairs * sizeof(int32_t));
   L.sell = take(npairs * sizeof(double));
+  L.midblk = take(npairs * sizeof(int32_t));
   L.svec = take(2 * size_t(npairs) * vstride * vbytes);
   L.total = off;
   return L;
@@ -381,6 +383,7 @@ static TraceParams resident_params(const hyb_model* m, int nc, void* ws, size_t 
   P.st_ell = reinterpret_cast<double*>(w + L.sell);
   P.st_vec = w + L.svec;
   P.vstride = (m->max_dim + 63) & ~63;
+  P.p_midblk = reinterpret_cast<int32_t*>(w + L.midblk);
   return P;
 }
 
@@ -415,6 +418,7 @@ int trace_resident(hyb_model* m, int nc, const int64_t* begin, const int64_t* en
   const Variant& V = kVariants[vi];
   TraceParams P = resident_params(m, nc, ws, V.fp64 ? sizeof(double) : sizeof(float));
   P.beta = beta;
+  P.tau_mid = 0.5 * beta;
   P.offsets = begin;
   P.ends = ends;
   P.tau = tau;
@@ -460,6 +464,14 @@ static void* scratch_of(int dev) {
 }
 
 int trace_resident_variant(const hyb_model* m) { return m->variant >= 0 ? m->variant : auto_variant(m); }
+
+ResidentPairs trace_resident_pairs(const hyb_model* m, int nc, void* ws) {
+  const int vi = m->variant >= 0 ? m->variant : auto_variant(m);
+  const ResidentLayout L = resident_layout(m, nc, kVariants[vi].fp64 ? sizeof(double) : sizeof(float));
+  char* w = static_cast<char*>(ws);
+  return {reinterpret_cast<const int8_t*>(w + L.psign), reinterpret_cast<const double*>(w + L.plog),
+          reinterpret_cast<const int32_t*>(w + L.midblk)};
+}
 
 }  // namespace hyb
 
@@ -902,6 +914,7 @@ int hyb_trace_batch_noalloc(hyb_model* m, const hyb_config_batch* cfg, double be
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   TraceParams P = resident_params(m, nc, ws, vbytes);
   P.beta = beta;
+  P.tau_mid = 0.5 * beta;
   P.offsets = cfg->offsets;
   P.ends = nullptr;
   P.tau = cfg->tau;

@@ -88,6 +88,10 @@ struct TraceParams {
   // rank among patterns of its popcount, and the spin-flip / pair-hopping amplitudes
   const int16_t* rank_half;
   double jsf, jph;
+  // optional: the block each (config, retained state) path occupies at time tau_mid
+  // (the block after every operator earlier than tau_mid); nullptr to skip
+  int32_t* p_midblk;
+  double tau_mid;
 };
 
 __device__ __forceinline__ int64_t cfg_end(const TraceParams& P, int c) {
@@ -1128,6 +1132,7 @@ __device__ inline void scan_pair(const TraceParams& P, int64_t id) {
   int err = 0;
   const BlockDev B0 = P.blocks[P.ret_block[r]];
   int nu = B0.n_up, nd = B0.n_dn;
+  int mid = P.ret_block[r];
   bool feas = true;
   double prev = -1.0;
   if (o1 < o0) err |= ERR_UNSORTED;
@@ -1144,7 +1149,9 @@ __device__ inline void scan_pair(const TraceParams& P, int64_t id) {
     const int step = dg ? 1 : -1;
     if (f < P.n_orb) nu += step; else nd += step;
     if (nu < 0 || nu > P.n_orb || nd < 0 || nd > P.n_orb) feas = false;
+    if (feas && t < P.tau_mid) mid = nd * (P.n_orb + 1) + nu;
   }
+  if (P.p_midblk) P.p_midblk[id] = feas ? mid : -1;
   if (nu != B0.n_up || nd != B0.n_dn) feas = false;
   if (err) feas = false;
   P.p_sign[id] = 0;

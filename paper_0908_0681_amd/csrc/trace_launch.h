@@ -28,4 +28,14 @@ int trace_resident(hyb_model* m, int n_configs, const int64_t* begin, const int6
 // hyb_set_trace_variant).
 int trace_resident_variant(const hyb_model* m);
 
+// Per (config, retained state) results of the last trace_resident on ws (pair id =
+// config * n_retained + r): sign and log of each path's contribution t_r, and the
+// block the path occupies at beta/2 (-1 for a path that leaves the physical range).
+struct ResidentPairs {
+  const int8_t* sign;
+  const double* log;
+  const int32_t* midblk;
+};
+ResidentPairs trace_resident_pairs(const hyb_model* m, int n_configs, void* ws);
+
 }  // namespace hyb

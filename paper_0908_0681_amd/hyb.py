@@ -115,6 +115,7 @@ _SIGS = {
     "hyb_mc_set_graphs": (C.c_int, [_P, C.c_int32]),
     "hyb_mc_save": (C.c_int, [_P, _P, C.POINTER(C.c_size_t), _P]),
     "hyb_mc_set_delta": (C.c_int, [_P, _P, _P]),
+    "hyb_mc_sector_weights": (C.c_int, [_P, _P, _P, _P]),
     "hyb_mc_get_delta": (C.c_int, [_P, _P]),
     "hyb_mc_bethe_delta": (C.c_int, [_P, C.c_double, C.c_double, C.c_int32, _P, _P]),
     "hyb_dmft_bethe": (C.c_int, [_P, C.POINTER(DmftParamsC), _P, _P, _P]),
@@ -522,6 +523,15 @@ class MC:
         """Restores a checkpoint written by save() (hyb_mc_load)."""
         buf = C.create_string_buffer(blob, len(blob))
         _check(lib().hyb_mc_load(self.h, buf, len(blob), _stream(stream)))
+
+    def sector_weights(self, stream=None):
+        """(weights [n_blocks], per-chain accumulators [n_chains][n_blocks]) of the
+        (n_up, n_dn) sectors at beta/2."""
+        nb = self.model.info()["n_blocks"]
+        w = np.zeros(nb)
+        acc = np.zeros((self.n_chains, nb))
+        _check(lib().hyb_mc_sector_weights(self.h, _ptr(w), _ptr(acc), _stream(stream)))
+        return w, acc
 
     def set_delta(self, delta, stream=None):
         """Replaces the Delta table (same grid); M, log|det| and signs rebuilt per chain."""

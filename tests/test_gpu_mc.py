@@ -8,7 +8,8 @@ uses O(k^2) determinant updates and the Krylov trace.  Bars:
 - M_f against inv(A_f): 1e-10 relative;
 - log|w|: 1e-10 absolute;
 - signs: exact;
-- G(tau) accumulators: 1e-9 relative.
+- G(tau) accumulators: 1e-9 relative;
+- sector weights at beta/2 (per chain, sign-weighted sums): 1e-9.
 The free-orbital run checks G(tau) = G_sc(tau) statistically.
 """
 import math
@@ -94,6 +95,9 @@ def _replay_and_compare(which, n_chains, n_moves, kmax=None, n_tau=20, meas_ever
     g, ms, nm = mc.accumulators()
     assert np.all(nm == n_moves // meas_every)
     assert np.max(np.abs(g - acc)) <= 1e-9 * max(1e-300, np.max(np.abs(acc)))
+    _, sec = mc.sector_weights()
+    sec_ref = np.stack([r["sec"] for r in reps])
+    assert np.max(np.abs(sec - sec_ref)) <= 1e-9 * max(1.0, np.max(np.abs(sec_ref)))
     stats = mc.stats()
     assert stats["moves"] == n_moves * setup.n_chains
     assert stats["insert_accepted"] + stats["remove_accepted"] == accepted
@@ -341,3 +345,26 @@ def test_mc_checkpoint_resume_bitwise():
     _same_chains(a, b)
     for x in (a, b, other):
         x.close()
+
+
+def test_mc_free_orbital_sector_weights():
+    """U = 0, eps = 0 (half filling): the four sectors 0, up, down, up+down each carry
+    weight 1/4 at beta/2 (<n_up n_dn> = <n_up><n_dn> = 1/4), within the spread over
+    independent chains."""
+    _require_gpu()
+    setup = I.mc_setup(5, 128)
+    w = setup.workload
+    m = hyb.model_for_workload(w)
+    mc = hyb.MC(m, setup.n_chains, w.beta, setup.delta, kmax=48, nmax_ops=256, seed=setup.seed, n_tau=20)
+    mc.sweep(500)
+    mc.reset_measurements()
+    mc.sweep(3000)
+    wts, acc = mc.sector_weights()
+    _, ms, _ = mc.accumulators()
+    per = acc / ms[:, None]
+    err = per.std(axis=0, ddof=1) / math.sqrt(setup.n_chains)
+    z = (wts - 0.25) / np.maximum(err, 1e-12)
+    print(f"free orbital sectors at beta/2: {np.round(wts, 4)} +- {np.round(err, 4)}")
+    assert wts.sum() == pytest.approx(1.0, abs=1e-12)
+    assert np.abs(z).max() < 5.0
+    mc.close()

@@ -540,3 +540,53 @@ def test_polynomial_and_eigen_propagators_agree():
     nz = r1.sign != 0
     assert np.max(np.abs(r1.log_abs[nz] - r2.log_abs[nz])) < 1e-12
 
+
+
+def test_sector_weights_against_dense_projector():
+    """The oracle's sector weights at tau_m (block walk over the retained-state paths)
+    against the plain definition on the full 2^F Fock space: the projector onto the
+    (n_up, n_dn) sector inserted at tau_m into the dense product
+    Tr_R[P_R e^{-(beta - tau_n) H} O_n ... Pi_s(tau_m) ... O_1 e^{-tau_1 H}] / Tr_R,
+    with R the retained eigenvectors of the full H (dense eigh, no blocks)."""
+    import scipy.linalg as sla
+    from oracle import fock as Fk
+    from oracle import hamiltonian as Hm
+    from paper_0908_0681_amd import inputs as I
+    w = I.workload(0)
+    for window in (-1.0, 1e-9):
+        o = T.build(w.params, window)
+        H = Hm.kanamori_full(w.params).toarray()
+        E, V = np.linalg.eigh(H)
+        keep = (E - E.min() <= window) if window >= 0 else np.ones(len(E), bool)
+        ops = Fk.FockOperators(2)
+        n = 2
+        blk = np.array([Fk.block_key(n, *Fk.spin_counts(n, s)) for s in range(16)])
+        b = w.batch(12)
+        for c in range(b.n_configs):
+            tau, fl, dg = b.config(c)
+            if len(tau) == 0:
+                continue
+            tm = 0.5 * b.beta
+            got = o.sector_weights(tau, fl, dg, b.beta, tm)
+            # dense product with the projector inserted at tm, factors latest leftmost
+            times = list(tau) + [tm]
+            kinds = [("op", int(fl[k]), int(dg[k])) for k in range(len(tau))] + [("proj",)]
+            order = np.argsort(times, kind="stable")
+            ref = {}
+            for s_b in sorted(set(blk)):
+                M = np.eye(16)
+                prev = 0.0
+                for j in order:
+                    M = sla.expm(-(times[j] - prev) * (H - E.min() * np.eye(16))) @ M
+                    prev = times[j]
+                    if kinds[j][0] == "op":
+                        M = ops.op(kinds[j][1], kinds[j][2]).toarray() @ M
+                    else:
+                        M = np.diag((blk == s_b).astype(float)) @ M
+                M = sla.expm(-(b.beta - prev) * (H - E.min() * np.eye(16))) @ M
+                ref[s_b] = float(np.sum([V[:, i] @ M @ V[:, i] for i in np.nonzero(keep)[0]]))
+            tot = sum(ref.values())
+            if abs(tot) < 1e-12 * max(abs(v) for v in ref.values()) or not got:
+                continue
+            for s_b, v in ref.items():
+                assert got.get(s_b, 0.0) == pytest.approx(v / tot, abs=1e-9), (window, c, s_b)
