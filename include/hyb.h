@@ -62,6 +62,9 @@ extern "C" {
                                 accumulation; float64 diagonal, Lanczos alpha/beta,
                                 re-orthogonalisation coefficients, tridiagonal exponential
                                 and running log-norm */
+#define HYB_SPECTRUM_HOST    0  /* hyb_model_create diagonalises every block on the host */
+#define HYB_SPECTRUM_DEVICE  1  /* no host eigensolver: E0, the block shifts and the retained
+                                   set come from hyb_init_lanczos on the device */
 
 typedef struct {
   int32_t n_orb;          /* orbitals, 1..7 (F = 2*n_orb flavors <= 14) */
@@ -82,6 +85,9 @@ typedef struct {
                              beta_m |[exp(-dtau T_m)]_{m,1}| / ||exp(-dtau T_m) e_1|| <= tol.
                              Sec. III step 5 leaves the criterion open; this is the
                              Saad (1992) estimate.  Typical 1e-13 (FP64), 1e-7 (mixed). */
+  int32_t spectrum;       /* HYB_SPECTRUM_HOST (0, the default of a zeroed struct) or
+                             HYB_SPECTRUM_DEVICE.  Sec. III step 1: full diagonalisation,
+                             or the lowest states by band Lanczos */
 } hyb_model_params;
 
 typedef struct hyb_model hyb_model;
@@ -96,7 +102,10 @@ typedef struct {
  * with spin-flip and pair-hopping summed once per ordered orbital pair a != b),
  * the spectrum of every block by dense FP64 Householder tridiagonalisation and
  * implicit QR with Wilkinson shifts (Sec. III step 1, full diagonalisation), E0 and the retained set
- * (step 2).  Host memory only; no GPU is touched.  *out receives a new handle. */
+ * (step 2).  With spectrum = HYB_SPECTRUM_DEVICE the eigensolver is skipped: E0 is NaN
+ * and the retained set empty until hyb_init_lanczos, and every call that needs them
+ * (traces, propagation, Monte Carlo, matrix formulation) returns HYB_E_STATE before.
+ * Host memory only; no GPU is touched.  *out receives a new handle. */
 int hyb_model_create(const hyb_model_params* p, hyb_model** out);
 
 /* Copies the model (basis tables, CSR blocks, retained vectors) to the current
@@ -106,6 +115,32 @@ int hyb_model_create(const hyb_model_params* p, hyb_model** out);
  * live until hyb_model_destroy. */
 int hyb_model_upload(hyb_model* m, void* stream);
 
+/* Device initialisation, Sec. III steps 1-2 by band Lanczos (for blocks too large to
+ * diagonalise fully): for every (n_up, n_dn) block, a block Krylov space of H_b from
+ * block_size pseudo-random start vectors, fully reorthogonalised (two Gram-Schmidt
+ * passes per vector; a vector with no new direction is replaced by a fresh one), its
+ * projection T diagonalised on the host.  Phase 1 takes every block to a converged
+ * lowest Ritz value, which fixes E0; phase 2 continues the blocks that reach within
+ * retain_window of E0 until every Ritz value up to E0 + retain_window and the first one
+ * above it have residual ||H x - theta x|| <= tol * ||H_b|| (||H_b|| bounded by the
+ * largest absolute row sum), or the space spans the block.  The Ritz vectors up to
+ * E0 + retain_window become the retained set (Sec. IV.C: an energy window, which near
+ * a level crossing holds the multiplets on both sides), E0 the smallest Ritz value,
+ * each block's shift its lowest one; the device copies are then rewritten as by
+ * hyb_model_upload (device pointers captured earlier, and a matrix formulation built
+ * earlier, become stale).  Works for HYB_SPECTRUM_HOST models too (it replaces their
+ * host retained set).  FP64 throughout: a custom SpMM kernel and rocBLAS DGEMM/DGEMV.
+ * Degeneracy: block Krylov holds at most block_size copies of a level, so a retained
+ * level found block_size times (space not spanning its block) is an HYB_E_ARG error;
+ * choose block_size above the largest in-block multiplicity of a retained level.
+ * steps / resid (host [n_blocks], may be NULL): block steps taken and the largest
+ * residual among a block's retained pairs (its lowest pair for other blocks).
+ * Errors: HYB_E_STATE (not uploaded, other device), HYB_E_ARG (retain_window < 0,
+ * block_size outside 2..64, tol outside [1e-15, 1e-4], multiplicity), HYB_E_NOCONV,
+ * HYB_E_OOM, HYB_E_HIP. */
+int hyb_init_lanczos(hyb_model* m, int32_t block_size, double tol, int32_t* steps, double* resid,
+                     void* stream);
+
 /* hyb_model_create + hyb_model_upload. */
 int hyb_build_hloc(const hyb_model_params* p, void* stream, hyb_model** out);
 
@@ -113,10 +148,13 @@ void hyb_model_destroy(hyb_model* m);
 
 int hyb_model_info(const hyb_model* m, hyb_model_info_t* out);
 
-/* Per-block data (host). dim / nnz_offdiag / e_min may be NULL. */
+/* Per-block data (host). dim / nnz_offdiag / e_min may be NULL.  e_min is the block's
+ * lowest eigenvalue (HYB_SPECTRUM_DEVICE: its lowest Ritz value, NaN before
+ * hyb_init_lanczos). */
 int hyb_block_info(const hyb_model* m, int32_t block, int32_t* dim, int32_t* nnz_offdiag, double* e_min);
 
-/* Block spectrum (host): e[0..dim) ascending eigenvalues of block `block`. */
+/* Block spectrum (host): e[0..dim) ascending eigenvalues of block `block`.  HYB_E_STATE
+ * for a HYB_SPECTRUM_DEVICE model (only its retained levels are known). */
 int hyb_block_eigenvalues(const hyb_model* m, int32_t block, double* e);
 
 /* Basis parity hooks (host): state integer <-> (block, index in block). */

@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libhyb.so")
 
-SOURCES = ["model.cpp", "eigen.cpp", "trace.hip", "spmm.hip", "mc.hip", "mlp.hip", "matrix.hip"]
+SOURCES = ["model.cpp", "eigen.cpp", "trace.hip", "spmm.hip", "mc.hip", "mlp.hip", "matrix.hip", "lanczos.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -110,4 +110,11 @@ namespace hyb {
 int sym_eig(int n, const double* a, double* evals, int n_vec, double* vec);
 void free_device(hyb_model* m);
 void matrix_release(hyb_model* m);  // matrix.hip: frees the matrix formulation's device data
+// 0 when E0 and the retained set exist (always with HYB_SPECTRUM_HOST; after
+// hyb_init_lanczos with HYB_SPECTRUM_DEVICE), else a state error.
+inline int require_spectrum(const hyb_model* m) {
+  return m->ret_block.empty() ? set_error(HYB_E_STATE, "no retained set yet: a model created with "
+                                          "HYB_SPECTRUM_DEVICE needs hyb_init_lanczos first")
+                              : 0;
+}
 }  // namespace hyb

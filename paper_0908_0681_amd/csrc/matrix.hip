@@ -305,6 +305,7 @@ extern "C" {
 int hyb_matrix_build(hyb_model* m, void* stream) {
   if (!m) return set_error(HYB_E_ARG, "NULL model");
   if (!m->uploaded) return set_error(HYB_E_STATE, "model not uploaded to a device");
+  if (int rc0 = require_spectrum(m)) return rc0;
   int dev = -1;
   MAT_HIP_TRY(hipGetDevice(&dev));
   if (dev != m->dev.device) return set_error(HYB_E_STATE, "model lives on device %d, current is %d", m->dev.device, dev);

@@ -364,6 +364,7 @@ int hyb_mc_create(hyb_model* m, const hyb_mc_params* p, hyb_mc** out) {
   if (!m || !p || !out) return set_error(HYB_E_ARG, "NULL argument");
   *out = nullptr;
   if (!m->uploaded) return set_error(HYB_E_STATE, "model not uploaded to a device");
+  if (int rc0 = require_spectrum(m)) return rc0;
   if (p->n_chains < 1 || p->n_chains > (1 << 20)) return set_error(HYB_E_ARG, "n_chains out of range");
   if (p->kmax < 1 || p->kmax > 63) return set_error(HYB_E_ARG, "kmax must be in 1..63");
   if (p->nmax_ops < 2 || p->nmax_ops > 4096) return set_error(HYB_E_ARG, "nmax_ops must be in 2..4096");

@@ -263,6 +263,8 @@ int hyb_model_create(const hyb_model_params* p, hyb_model** out) {
   if (p->precision != HYB_FP64 && p->precision != HYB_MIXED)
     return set_error(HYB_E_ARG, "unknown precision %d", p->precision);
   if (p->krylov_max < 2 || p->krylov_max > 20) return set_error(HYB_E_ARG, "krylov_max must be in 2..20");
+  if (p->spectrum != HYB_SPECTRUM_HOST && p->spectrum != HYB_SPECTRUM_DEVICE)
+    return set_error(HYB_E_ARG, "unknown spectrum mode %d", p->spectrum);
   if (!(p->krylov_tol > 0.0) || !(p->krylov_tol < 1.0)) return set_error(HYB_E_ARG, "krylov_tol must be in (0,1)");
   const double vals[] = {p->U, p->Up, p->J, p->J_sf, p->J_ph, p->retain_window};
   for (double v : vals)
@@ -277,7 +279,8 @@ int hyb_model_create(const hyb_model_params* p, hyb_model** out) {
   m->n_orb = p->n_orb;
   int rc = build_basis(*m);
   if (!rc) rc = build_hamiltonian(*m);
-  if (!rc) rc = build_spectrum(*m);
+  if (!rc && p->spectrum == HYB_SPECTRUM_HOST) rc = build_spectrum(*m);
+  if (!rc && p->spectrum == HYB_SPECTRUM_DEVICE) m->E0 = NAN;  // hyb_init_lanczos supplies it
   if (rc) {
     delete m;
     return rc;
@@ -312,13 +315,21 @@ int hyb_block_info(const hyb_model* m, int32_t b, int32_t* dim, int32_t* nnz, do
   const BlockDev& B = m->blocks[b];
   if (dim) *dim = B.dim;
   if (nnz) *nnz = m->rowptr[B.state_off + B.dim] - m->rowptr[B.state_off];
-  if (emin) *emin = B.dim ? m->evals[b][0] : 0.0;
+  if (emin) {
+    if (!B.dim)
+      *emin = 0.0;
+    else if (!m->evals.empty())
+      *emin = m->evals[b][0];
+    else  // device spectrum: the lowest Ritz value, once computed
+      *emin = m->ret_block.empty() ? NAN : B.shift;
+  }
   return HYB_OK;
 }
 
 int hyb_block_eigenvalues(const hyb_model* m, int32_t b, double* e) {
   if (!m || !e) return set_error(HYB_E_ARG, "NULL argument");
   if (b < 0 || b >= m->n_blocks) return set_error(HYB_E_ARG, "block %d out of range", b);
+  if (m->evals.empty()) return set_error(HYB_E_STATE, "spectrum computed on the device: only retained levels are known");
   std::copy(m->evals[b].begin(), m->evals[b].end(), e);
   return HYB_OK;
 }

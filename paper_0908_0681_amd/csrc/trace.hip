@@ -231,9 +231,9 @@ static int auto_variant(const hyb_model* m) {
 
 template <typename T>
 static int dev_upload(T*& dst, const T* src, size_t n, hipStream_t s) {
-  if (n == 0) n = 1;
-  HIP_TRY(hipMalloc(reinterpret_cast<void**>(&dst), n * sizeof(T)));
-  if (src) HIP_TRY(hipMemcpyAsync(dst, src, n * sizeof(T), hipMemcpyHostToDevice, s));
+  // an empty array gets a one-element placeholder and no copy
+  HIP_TRY(hipMalloc(reinterpret_cast<void**>(&dst), std::max<size_t>(n, 1) * sizeof(T)));
+  if (src && n) HIP_TRY(hipMemcpyAsync(dst, src, n * sizeof(T), hipMemcpyHostToDevice, s));
   return 0;
 }
 
@@ -659,6 +659,7 @@ int hyb_last_timing(const hyb_model* m, float* ms) {
 int hyb_trace_batch(hyb_model* m, const hyb_config_batch* cfg, double beta, hyb_trace_out* out, void* stream) {
   if (!m || !cfg || !out) return set_error(HYB_E_ARG, "NULL argument");
   if (!m->uploaded) return set_error(HYB_E_STATE, "model not uploaded to a device");
+  if (int rc0 = require_spectrum(m)) return rc0;
   if (!(beta > 0.0) || !std::isfinite(beta)) return set_error(HYB_E_ARG, "beta must be positive and finite");
   if (cfg->n_configs < 0) return set_error(HYB_E_ARG, "negative n_configs");
   if (cfg->n_configs == 0) return HYB_OK;
@@ -887,6 +888,7 @@ int hyb_trace_batch_noalloc(hyb_model* m, const hyb_config_batch* cfg, double be
                             void* stream) {
   if (!m || !cfg || !out) return set_error(HYB_E_ARG, "NULL argument");
   if (!m->uploaded) return set_error(HYB_E_STATE, "model not uploaded to a device");
+  if (int rc0 = require_spectrum(m)) return rc0;
   if (!(beta > 0.0) || !std::isfinite(beta)) return set_error(HYB_E_ARG, "beta must be positive and finite");
   if (cfg->n_configs < 0) return set_error(HYB_E_ARG, "negative n_configs");
   if (cfg->n_configs == 0) return HYB_OK;
@@ -958,6 +960,7 @@ int hyb_propagate_device(hyb_model* m, int32_t block, int32_t n_vec, const void*
                          double* log_scale, int32_t* steps, void* stream) {
   if (!m || !x || !dtau || !y || !log_scale) return set_error(HYB_E_ARG, "NULL argument");
   if (!m->uploaded) return set_error(HYB_E_STATE, "model not uploaded");
+  if (int rc0 = require_spectrum(m)) return rc0;
   if (block < 0 || block >= m->n_blocks || n_vec < 0) return set_error(HYB_E_ARG, "bad block / count");
   if (m->blocks[block].dim == 0 || n_vec == 0) return HYB_OK;
   const int vi = m->variant >= 0 ? m->variant : auto_variant(m);

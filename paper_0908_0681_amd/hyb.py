@@ -20,6 +20,7 @@ ERRORS = {-1: "HYB_E_ARG", -2: "HYB_E_UNSORTED", -3: "HYB_E_FLAVOR", -4: "HYB_E_
           -5: "HYB_E_NONFINITE", -6: "HYB_E_HIP", -7: "HYB_E_OOM", -8: "HYB_E_STATE"}
 HYB_CSR, HYB_MATRIX_FREE = 0, 1
 HYB_FP64, HYB_MIXED = 0, 1
+HYB_SPECTRUM_HOST, HYB_SPECTRUM_DEVICE = 0, 1
 
 
 class HybError(RuntimeError):
@@ -32,7 +33,7 @@ class ModelParamsC(C.Structure):
     _fields_ = [("n_orb", C.c_int32), ("eps", C.POINTER(C.c_double)), ("U", C.c_double),
                 ("Up", C.c_double), ("J", C.c_double), ("J_sf", C.c_double), ("J_ph", C.c_double),
                 ("storage", C.c_int32), ("precision", C.c_int32), ("retain_window", C.c_double),
-                ("krylov_max", C.c_int32), ("krylov_tol", C.c_double)]
+                ("krylov_max", C.c_int32), ("krylov_tol", C.c_double), ("spectrum", C.c_int32)]
 
 
 class ModelInfoC(C.Structure):
@@ -77,6 +78,7 @@ _SIGS = {
     "hyb_model_create": (C.c_int, [C.POINTER(ModelParamsC), C.POINTER(_P)]),
     "hyb_model_upload": (C.c_int, [_P, _P]),
     "hyb_build_hloc": (C.c_int, [C.POINTER(ModelParamsC), _P, C.POINTER(_P)]),
+    "hyb_init_lanczos": (C.c_int, [_P, C.c_int32, C.c_double, _P, _P, _P]),
     "hyb_model_destroy": (None, [_P]),
     "hyb_model_info": (C.c_int, [_P, C.POINTER(ModelInfoC)]),
     "hyb_block_info": (C.c_int, [_P, C.c_int32, _P, _P, _P]),
@@ -203,22 +205,41 @@ class Model:
     """Owns a hyb_model handle."""
 
     def __init__(self, params, precision="fp64", retain_window=1e-5, krylov_max=12,
-                 krylov_tol=None, upload=True, stream=None, storage="csr"):
+                 krylov_tol=None, upload=True, stream=None, storage="csr", spectrum="host",
+                 lanczos_block=8, lanczos_tol=1e-12):
+        """spectrum="device": no host eigensolver; after the upload hyb_init_lanczos
+        (block size lanczos_block, residual tolerance lanczos_tol) supplies E0 and the
+        retained set (its per-block steps and residuals in self.lanczos)."""
         prec = {"fp64": HYB_FP64, "mixed": HYB_MIXED}[precision]
         store = {"csr": HYB_CSR, "matrix_free": HYB_MATRIX_FREE}[storage]
+        spec = {"host": HYB_SPECTRUM_HOST, "device": HYB_SPECTRUM_DEVICE}[spectrum]
         if krylov_tol is None:
             krylov_tol = 1e-13 if prec == HYB_FP64 else 1e-7
         self._eps = np.ascontiguousarray(params.eps, dtype=np.float64)
         p = ModelParamsC(n_orb=params.n_orb, eps=self._eps.ctypes.data_as(C.POINTER(C.c_double)),
                          U=params.U, Up=params.Up, J=params.J, J_sf=params.J_sf, J_ph=params.J_ph,
                          storage=store, precision=prec, retain_window=retain_window,
-                         krylov_max=krylov_max, krylov_tol=krylov_tol)
+                         krylov_max=krylov_max, krylov_tol=krylov_tol, spectrum=spec)
         h = C.c_void_p()
         _check(lib().hyb_model_create(C.byref(p), C.byref(h)))
         self.h = h
         self.precision = precision
+        self.lanczos = None
         if upload:
             self.upload(stream)
+            if spec == HYB_SPECTRUM_DEVICE:
+                self.init_lanczos(lanczos_block, lanczos_tol, stream)
+
+    def init_lanczos(self, block_size=8, tol=1e-12, stream=None):
+        """hyb_init_lanczos: E0, block shifts and the retained set by band Lanczos on the
+        device.  Returns (and keeps in self.lanczos) the block steps and the largest
+        retained-pair residual of every block."""
+        nb = self.info()["n_blocks"]
+        steps = np.zeros(nb, np.int32)
+        resid = np.zeros(nb)
+        _check(lib().hyb_init_lanczos(self.h, block_size, tol, _ptr(steps), _ptr(resid), _stream(stream)))
+        self.lanczos = {"steps": steps, "resid": resid}
+        return self.lanczos
 
     def upload(self, stream=None):
         _check(lib().hyb_model_upload(self.h, _stream(stream)))

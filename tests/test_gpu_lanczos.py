@@ -1,0 +1,174 @@
+"""GPU parity of the device initialisation (hyb_init_lanczos: band Lanczos per block,
+Sec. III steps 1-2, with the energy window of Sec. IV.C) through the C ABI.
+
+Reference: the oracle's dense FP64 eigendecomposition of every block and its retained
+set R = {E_i - E0 <= window}.  Bars:
+- the same retained blocks in the same order (block, then energy), so the same N_tr;
+- energies and E0 within 1e-9 absolute;
+- the retained subspace of every block: the projector X X^T within
+  max(1e-8, 10 r / g) of the oracle's (Davis-Kahan: a residual r moves an eigenvector by
+  at most r / g, g the gap to the nearest level outside the retained set of the block;
+  the projector is compared, not the vectors, because a degenerate level's basis is
+  free up to a rotation);
+- traces of a device-initialised model against the oracle: relative error 1e-10 (the
+  FP64 trace bar), signs and feasible-path counts exact.
+"""
+import math
+import sys
+import time
+
+import numpy as np
+import pytest
+
+from paper_0908_0681_amd import inputs as I
+from paper_0908_0681_amd import hyb
+from oracle import hamiltonian as Hm
+from oracle import pool as OP
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(autouse=True)
+def announce(request):
+    print(f"\n[gpu-test] {request.node.nodeid}", flush=True)
+    sys.stdout.flush()
+    yield
+
+
+def _require_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _crossing(dmu):
+    return I.kanamori(5, U=6.0, J=1.0, mu=I.mu_half(5, 6.0, 1.0) + dmu)
+
+
+# name -> (parameters, window, expected N_tr or None)
+CASES = {
+    "5orb-cf": (lambda: I.workload(1).params, 1e-5, 6),
+    "3orb-U6": (lambda: I.comparator_workload(3).params, 1e-5, 4),
+    "6orb-U6": (lambda: I.comparator_workload(6).params, 1e-5, 7),
+    "7orb-cf": (lambda: I.workload(2).params, 1e-5, 8),
+    "5orb-mu4.98": (lambda: _crossing(4.98), 1e-5, 6),
+    "5orb-mu5.00": (lambda: _crossing(5.0), 1e-5, 31),
+    "5orb-mu5.02": (lambda: _crossing(5.02), 1e-5, 25),
+    # the energy window across the crossing holds both multiplets (Sec. IV.C)
+    "5orb-mu4.98-window0.05": (lambda: _crossing(4.98), 0.05, 31),
+}
+
+
+def _retained_by_block(blk, vec, dims):
+    out, off = {}, 0
+    for b in blk:
+        d = dims[int(b)]
+        out.setdefault(int(b), []).append(vec[off:off + d])
+        off += d
+    return {b: np.array(v).T for b, v in out.items()}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_device_spectrum_matches_oracle(name):
+    _require_gpu()
+    mk, window, ntr = CASES[name]
+    params = mk()
+    t0 = time.perf_counter()
+    m = hyb.Model(params, precision="fp64", retain_window=window, spectrum="device", lanczos_block=8,
+                  lanczos_tol=1e-13)
+    t_dev = time.perf_counter() - t0
+    spec = Hm.block_spectrum(params)
+    R = Hm.retained_set(spec, window)
+    info = m.info()
+    assert info["n_retained"] == len(R.block) == ntr
+    blk, en, vec = m.retained()
+    assert np.array_equal(blk, R.block)
+    assert np.max(np.abs(en - R.energy)) <= 1e-9, np.max(np.abs(en - R.energy))
+    assert abs(info["E0"] - spec.E0) <= 1e-9
+    dims = [len(s) for s in spec.states]
+    got = _retained_by_block(blk, vec, dims)
+    worst = 0.0
+    for b, X in got.items():
+        idx = R.index[R.block == b]
+        V = spec.V[b][:, idx]
+        # residual of each device Ritz pair (host product) and the gap to the rest
+        Hb = spec.H[b]
+        e_b = R.energy[R.block == b]
+        r = max(np.linalg.norm(Hb @ X[:, i] - e_b[i] * X[:, i]) for i in range(X.shape[1]))
+        rest = np.delete(spec.E[b], idx)
+        g = np.min(np.abs(rest[:, None] - e_b[None, :])) if len(rest) else np.inf
+        dP = np.max(np.abs(X @ X.T - V @ V.T))
+        worst = max(worst, dP)
+        assert dP <= max(1e-8, 10 * r / g), (b, dP, r, g)
+    st = m.lanczos["steps"]
+    print(f"{name}: N_tr {ntr}, E0 {info['E0']:.10f}, projector error {worst:.1e}, block steps {int(st.sum())} "
+          f"(max {int(st.max())}), largest residual {m.lanczos['resid'].max():.1e}, init {t_dev:.2f} s")
+
+
+@pytest.mark.parametrize("name,n", [("5orb-cf", 64), ("5orb-mu5.00", 48), ("5orb-mu4.98-window0.05", 48)])
+def test_traces_of_device_initialised_model(name, n):
+    _require_gpu()
+    mk, window, _ = CASES[name]
+    params = mk()
+    m = hyb.Model(params, precision="fp64", retain_window=window, spectrum="device", lanczos_tol=1e-13,
+                  krylov_max=12, krylov_tol=1e-13)
+    b = I.random_batch(2024, params.n_orb, n, 50.0, 5.0)
+    ref, _ = OP.trace_batch(params, window, b)
+    res = m.trace_batch(b, beta=50.0)
+    kap = ref.kappa()
+    worst = 0.0
+    for c in range(n):
+        so, sg = int(ref.sign[c]), int(res.sign[c])
+        if so == 0:
+            assert sg == 0 and res.log_abs[c] == -math.inf, c
+            continue
+        assert sg == so, (c, sg, so, kap[c])
+        d = float(res.log_abs[c] - ref.log_abs[c])
+        err = abs(math.expm1(d)) if kap[c] <= 10 else abs(math.exp(d) - 1.0) / kap[c]
+        worst = max(worst, err)
+        assert err <= 1e-10, (c, err, kap[c])
+    assert np.array_equal(res.feasible_paths, ref.feasible.sum(axis=1))
+    print(f"{name}: worst relative trace error {worst:.2e} over {n} configurations")
+
+
+def test_degenerate_level_needs_a_larger_block():
+    """At the crossing a retained level appears 5 times in one block; block size 4
+    cannot certify it and is refused, block size 8 is not."""
+    _require_gpu()
+    p = _crossing(5.0)
+    m = hyb.Model(p, precision="fp64", retain_window=1e-5, spectrum="device", upload=False)
+    m.upload()
+    with pytest.raises(hyb.HybError) as e:
+        m.init_lanczos(4, 1e-13)
+    assert e.value.code == -1 and "multiplicity" in str(e.value)
+    m.init_lanczos(8, 1e-13)
+    assert m.info()["n_retained"] == 31
+
+
+def test_states_and_arguments():
+    _require_gpu()
+    w = I.workload(1)
+    m = hyb.Model(w.params, precision="fp64", retain_window=w.retain_window, spectrum="device", upload=False)
+    assert math.isnan(m.info()["E0"]) and m.info()["n_retained"] == 0
+    m.upload()
+    b = w.batch(4)
+    with pytest.raises(hyb.HybError) as e:
+        m.trace_batch(b)
+    assert e.value.code == -8
+    for bs, tol in ((1, 1e-12), (65, 1e-12), (8, 0.0), (8, 1e-3)):
+        with pytest.raises(hyb.HybError) as e:
+            m.init_lanczos(bs, tol)
+        assert e.value.code == -1
+    m.init_lanczos(8, 1e-13)
+    r = m.trace_batch(b)
+    assert np.all(np.isin(r.sign, (-1, 0, 1)))
+    # a host-spectrum model can take the device retained set too
+    h = hyb.Model(w.params, precision="fp64", retain_window=w.retain_window)
+    e_host = h.retained()[1]
+    h.init_lanczos(8, 1e-13)
+    assert np.max(np.abs(h.retained()[1] - e_host)) <= 1e-9
+    # a full trace (negative window) stays with the host eigensolver
+    f = hyb.Model(w.params, precision="fp64", retain_window=-1.0)
+    with pytest.raises(hyb.HybError) as e:
+        f.init_lanczos(8, 1e-13)
+    assert e.value.code == -1

@@ -176,3 +176,27 @@ def test_storage_argument():
                          krylov_tol=1e-12)
     h = hyb.C.c_void_p()
     assert hyb.lib().hyb_model_create(hyb.C.byref(C), hyb.C.byref(h)) == -1
+
+
+def test_device_spectrum_mode_host_side():
+    """HYB_SPECTRUM_DEVICE skips the host eigensolver: no E0, no retained set, no block
+    spectrum until hyb_init_lanczos, which needs an uploaded model."""
+    w = I.workload(1)
+    m = hyb.Model(w.params, precision="fp64", retain_window=w.retain_window, spectrum="device", upload=False)
+    info = m.info()
+    assert np.isnan(info["E0"]) and info["n_retained"] == 0 and info["n_states"] == 1024
+    with pytest.raises(hyb.HybError) as e:
+        m.block_eigenvalues(12)
+    assert e.value.code == -8
+    assert np.isnan(m.block_info(12)[2])
+    # the Hamiltonian is built all the same
+    o = T.build(w.params, w.retain_window)
+    assert np.max(np.abs(m.block_dense(12) - o.spec.H[12])) <= 1e-13 * np.abs(o.spec.H[12]).max()
+    with pytest.raises(hyb.HybError) as e:
+        m.init_lanczos(8, 1e-12)
+    assert e.value.code == -8
+    p = hyb.ModelParamsC(n_orb=2, eps=(ctypes.c_double * 2)(-1.0, -1.0), U=4.0, Up=2.0, J=1.0, J_sf=1.0,
+                         J_ph=1.0, storage=0, precision=0, retain_window=1e-5, krylov_max=12, krylov_tol=1e-12,
+                         spectrum=2)
+    h = ctypes.c_void_p()
+    assert hyb.lib().hyb_model_create(ctypes.byref(p), ctypes.byref(h)) == -1
