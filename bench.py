@@ -254,7 +254,12 @@ def _mc_run(hyb, I, params, window, beta, n_chains, therm, meas, n_tau, seed, pr
     delta = I.semicircle_delta(beta, 1000)
     mc = hyb.MC(m, n_chains, beta, delta, kmax=60, nmax_ops=1024, seed=seed, n_tau=n_tau)
     t0 = time.perf_counter()
-    mc.sweep(therm)
+    gate = None
+    if isinstance(therm, tuple):
+        # thermalise until the mean order and G(beta/2) are stationary
+        gate = _thermalise(mc, beta, n_tau, chunk=1000, min_moves=therm[0], max_moves=therm[1])
+    else:
+        mc.sweep(therm)
     mc.reset_measurements()
     mc.sweep(meas)
     wall = time.perf_counter() - t0
@@ -262,10 +267,18 @@ def _mc_run(hyb, I, params, window, beta, n_chains, therm, meas, n_tau, seed, pr
     G, Gse = _ratio_jackknife(sgt, ms)
     _, sec = mc.sector_weights()
     P, Pse = _ratio_jackknife(sec, ms)
+    # <S^2> = 3 <S_z^2> (H_loc and the bath are SU(2) invariant) and <N>, both functions
+    # of the sector at beta/2
+    n = params.n_orb
+    b = np.arange(sec.shape[1])
+    nu, nd = b % (n + 1), b // (n + 1)
+    S2, S2se = _ratio_jackknife(sec @ (0.75 * (nu - nd) ** 2.0), ms)
+    Nn, Nse = _ratio_jackknife(sec @ (nu + nd).astype(np.float64), ms)
     st = mc.stats()
     info = m.info()
     mc.close()
-    return {"G": G, "G_se": Gse, "P": P, "P_se": Pse, "n_retained": info["n_retained"], "wall_s": wall,
+    return {"G": G, "G_se": Gse, "P": P, "P_se": Pse, "S2": float(S2), "S2_se": float(S2se), "N": float(Nn),
+            "N_se": float(Nse), "n_retained": info["n_retained"], "wall_s": wall, "thermalisation": gate,
             "mean_order": st["order_sum"] / max(1, st["moves"]), "sign_avg": st["sign_sum"] / max(1, st["moves"]),
             "acceptance": (st["insert_accepted"] + st["remove_accepted"]) / max(1, st["moves"])}
 
@@ -322,6 +335,43 @@ def measure_truncation_study(torch, hyb, I, n_chains=256, n_tau=40):
                                                    "max_abs_z": float(np.max(np.abs(z)))}
     out["fig4_comparison"] = cmp
     return out
+
+
+def measure_spin_study(torch, hyb, I, j_over_u=(0.0, 0.05, 0.1, 0.15, 0.2, 0.25), deltas=(0.0, 0.5),
+                       n_chains=128, therm=(4000, 20000), meas=4000, n_tau=40):
+    """Sec. V.C (Fig. 7) analogue: <S^2> at beta/2 against J/U for 5 orbitals at U = 2,
+    beta = 50, six electrons, degenerate orbitals and a crystal field Delta that lowers two
+    orbitals by 0.5.  The impurity sits in the semicircular bath of bandwidth 4 (no
+    self-consistency), mu at the middle of the six-electron plateau of H_loc, the ground
+    multiplet retained.  Measurement starts once the mean order and G(beta/2) are
+    stationary (therm = (min, max) moves of the gate).  Errors: jackknife over
+    independent chains."""
+    import numpy as np
+    n, U, beta = 5, 2.0, 50.0
+    rows = []
+    for dl in deltas:
+        delta = np.array([dl, dl, 0.0, 0.0, 0.0])
+        for ju in j_over_u:
+            J = ju * U
+            # lowest energy per particle number at mu = 0 -> the N = 6 plateau
+            h = hyb.Model(I.kanamori(n, U=U, J=J, mu=0.0, delta=delta), precision="fp64", retain_window=1e-5,
+                          upload=False)
+            emin = {}
+            for b in range(h.info()["n_blocks"]):
+                Nb = b % (n + 1) + b // (n + 1)
+                emin[Nb] = min(emin.get(Nb, np.inf), h.block_info(b)[2])
+            h.close()
+            mu = 0.5 * (emin[7] - emin[5])
+            r = _mc_run(hyb, I, I.kanamori(n, U=U, J=J, mu=mu, delta=delta), 1e-5, beta, n_chains, therm, meas,
+                        n_tau, 71)
+            row = {"delta": dl, "J_over_U": ju, "mu": mu, "n_tr": r["n_retained"], "S2": r["S2"],
+                   "S2_se": r["S2_se"], "N": r["N"], "N_se": r["N_se"], "mean_order": r["mean_order"],
+                   "sign_avg": r["sign_avg"], "thermalisation": r["thermalisation"], "seconds": r["wall_s"]}
+            print(f"[spin] Delta {dl} J/U {ju}: N_tr {row['n_tr']}, <S^2> {row['S2']:.3f} +- {row['S2_se']:.3f}, "
+                  f"<N> {row['N']:.3f}, order {row['mean_order']:.1f}, {row['seconds']:.0f} s", file=sys.stderr,
+                  flush=True)
+            rows.append(row)
+    return rows
 
 
 def measure_spmm(torch, hyb, I, n_vec=262144, reps=10):
@@ -472,7 +522,7 @@ def _thermalise(mc, beta, n_tau, chunk=1000, min_moves=6000, max_moves=30000):
             t_o, t_g = _drift_t(prev[0], cur[0]), _drift_t(prev[1], cur[1])
             hist.append((done, float(order.mean()), t_o, t_g))
             ok_run = ok_run + 1 if (abs(t_o) < 2.0 and abs(t_g) < 2.0) else 0
-            print(f"[ess] thermalising: {done} moves, mean order {order.mean():.2f}, t(order) {t_o:+.2f}, "
+            print(f"[therm] {done} moves, mean order {order.mean():.2f}, t(order) {t_o:+.2f}, "
                   f"t(G(beta/2)) {t_g:+.2f}", file=sys.stderr, flush=True)
             if done >= min_moves and ok_run >= 2:
                 break
@@ -714,6 +764,12 @@ def main():
     ap.add_argument("--comparator-only", action="store_true", help="only the Krylov vs matrix comparison")
     ap.add_argument("--truncation-study", action="store_true",
                     help="only the truncation study (3-orbital G(tau) N_tr = 4 vs full; 5-orbital sectors at beta/2)")
+    ap.add_argument("--spin-study", default="", metavar="J/U,...",
+                    help="only the total-spin study: <S^2> at beta/2 for 5 orbitals, U = 2, six electrons, at "
+                         "these J/U values (comma separated; 'all' for 0,0.05,0.1,0.15,0.2,0.25)")
+    ap.add_argument("--spin-chains", type=int, default=128, help="chains per point of the spin study")
+    ap.add_argument("--spin-moves", default="4000,8000",
+                    help="least thermalisation moves (the gate may take up to 5x) and measured moves of the spin study")
     ap.add_argument("--seven-only", action="store_true", help="only the 7-orbital mixed workload (profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (3 times) and exit: the reference "
@@ -750,6 +806,14 @@ def main():
         return
     if a.truncation_study:
         print(json.dumps({"truncation_study": measure_truncation_study(torch, hyb, I)}), flush=True)
+        return
+    if a.spin_study:
+        ju = (0.0, 0.05, 0.1, 0.15, 0.2, 0.25) if a.spin_study == "all" else \
+            tuple(float(x) for x in a.spin_study.split(","))
+        th, me = (int(x) for x in a.spin_moves.split(","))
+        th = (th, 5 * th)  # the stationarity gate: at least th, at most 5 th moves
+        print(json.dumps({"spin_study": measure_spin_study(torch, hyb, I, j_over_u=ju, n_chains=a.spin_chains,
+                                                           therm=th, meas=me)}), flush=True)
         return
     if a.comparator_only:
         print(json.dumps({"matrix_vs_krylov": measure_comparator(torch, hyb, I)}), flush=True)
@@ -790,12 +854,22 @@ def main():
                                       "substeps", "depth_histogram", "feasible_paths", "path_bytes",
                                       "host_buffers")},
     }
+    t_leg = time.perf_counter()
+
+    def leg(name):
+        nonlocal t_leg
+        now = time.perf_counter()
+        print(f"[bench] {name}: {now - t_leg:.1f} s", file=sys.stderr, flush=True)
+        t_leg = now
+
+    leg("5-orbital trace")
     if not a.no_seven:
         r7 = measure_workload(2, max(2, a.steps // 5), 1, torch, hyb, I)
         line["detail"]["kanamori-7orb-b40"] = {k: r7[k] for k in (
             "traces_per_s", "ms_per_step", "prop_ms", "prop_launches", "prop_bytes", "path_bytes",
             "mean_krylov_depth", "substeps", "feasible_paths", "host_buffers")}
         line["detail"]["kanamori-7orb-b40"]["roofline"] = roofline(r7, TRAFFIC.get(r7["workload"]))
+        leg("7-orbital trace")
     if not a.no_mc:
         line["detail"]["mc"] = measure_mc(torch, hyb, I)
         line["detail"]["mc"]["graph_replay"] = measure_mc(torch, hyb, I, graphs=True, moves_per_sweep=10)
@@ -803,13 +877,17 @@ def main():
             "direct": measure_mc(torch, hyb, I, moves=2000, warm=200, which=6, n_chains=256),
             "graph_replay": measure_mc(torch, hyb, I, moves=2000, warm=200, which=6, n_chains=256, graphs=True,
                                        moves_per_sweep=100)}
+        leg("Monte Carlo")
     if not a.no_spmm:
         line["detail"]["spmm_gated"] = measure_spmm(torch, hyb, I)
+        leg("SpMM")
     if not a.no_comparator:
         line["detail"]["matrix_vs_krylov"] = measure_comparator(torch, hyb, I)
+        leg("matrix vs Krylov")
     if not a.no_ess:
         line["detail"]["ess"] = measure_ess(torch, hyb, I, pairs=a.ess_pairs, target_se=a.ess_target,
                                             max_moves=a.ess_max_moves, eps=a.ess_eps, seed_offset=a.ess_seed)
+        leg("ESS")
     if not a.no_cpu:
         line["cpu_baseline"] = cpu_baseline(1, a.cpu_sample)
         if not a.no_seven:
@@ -820,6 +898,7 @@ def main():
         ofp = oracle_feasible_paths(1)
         line["detail"]["oracle_feasible_paths"] = ofp
         line["detail"]["feasible_paths_match"] = ofp == line["detail"]["feasible_paths"]
+        leg("CPU baseline")
     print(json.dumps(line), flush=True)
 
 

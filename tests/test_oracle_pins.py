@@ -590,3 +590,38 @@ def test_sector_weights_against_dense_projector():
                 continue
             for s_b, v in ref.items():
                 assert got.get(s_b, 0.0) == pytest.approx(v / tot, abs=1e-9), (window, c, s_b)
+
+
+def test_total_spin_from_sector_weights():
+    """<S^2> at beta/2 as 3 <S_z^2>, with S_z = (n_up - n_dn)/2 a function of the
+    (n_up, n_dn) sector, i.e. from the oracle's sector weights (Sec. V.C measures
+    <S^2>).  The reading rests on the SU(2) invariance of H_loc (Eq.(4) with each
+    ordered pair summed once) and of a spin-independent bath.  Pinned on configurations
+    without hybridisation events, where the weights are thermal: against Tr[rho S^2]
+    with the dense S^2 = S^- S^+ + S_z^2 + S_z on the full Fock space and rho the
+    (retained) thermal state of the full H; and against S(S+1) = 15/4 for the
+    half-filled 3-orbital ground quartet (S = 3/2)."""
+    from oracle import fock as Fk
+    from oracle import hamiltonian as Hm
+    from paper_0908_0681_amd import inputs as I
+    cases = [(I.workload(0).params, 10.0, -1.0), (I.workload(0).params, 2.0, -1.0),
+             (I.kanamori(3, U=6.0, J=1.0, mu=2.5 * 6.0 - 5.0), 1.5, -1.0),
+             (I.kanamori(3, U=6.0, J=1.0, mu=2.5 * 6.0 - 5.0), 50.0, 1e-9)]
+    for params, beta, window in cases:
+        n = params.n_orb
+        ops = Fk.FockOperators(n)
+        dim = 1 << (2 * n)
+        Sp = sum((ops.cdag[a] @ ops.c[a + n]) for a in range(n)).toarray()
+        Sz = 0.5 * sum((ops.n[a] - ops.n[a + n]) for a in range(n)).toarray()
+        S2 = Sp.T @ Sp + Sz @ Sz + Sz
+        H = Hm.kanamori_full(params).toarray()
+        E, V = np.linalg.eigh(H)
+        keep = (E - E.min() <= window) if window >= 0 else np.ones(dim, bool)
+        wts = np.exp(-beta * (E - E.min())) * keep
+        ref = float(np.sum(wts * np.einsum("ji,jk,ki->i", V, S2, V)) / wts.sum())
+        o = T.build(params, window)
+        P = o.sector_weights(np.zeros(0), np.zeros(0, np.int64), np.zeros(0, np.int64), beta, 0.5 * beta)
+        got = 3.0 * sum(p * (0.25 * (b % (n + 1) - b // (n + 1)) ** 2) for b, p in P.items())
+        assert got == pytest.approx(ref, abs=1e-10), (n, beta, window, got, ref)
+        if window >= 0:
+            assert got == pytest.approx(15.0 / 4.0, abs=1e-12)
