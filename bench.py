@@ -28,7 +28,7 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch of the path kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE,
 # scaled by the same counters on a plain 1 GiB device copy (FETCH_SIZE x2.0,
 # WRITE_SIZE x1.0); None once the kernel changes after the counters were taken.
-TRAFFIC = {"kanamori-5orb-b50": 24_981_260.0}
+TRAFFIC = {"kanamori-5orb-b50": 25_160_768.0, "kanamori-7orb-b40": 138_759_821.0}
 
 
 def device_batch(batch, torch):
@@ -245,14 +245,20 @@ def measure_comparator(torch, hyb, I, orbitals=(2, 3, 4, 5, 6, 7), n_configs=512
     return rows
 
 
-def _mc_run(hyb, I, params, window, beta, n_chains, therm, meas, n_tau, seed, precision="fp64"):
-    """Chains from empty configurations on the semicircular bath: therm moves, then meas
-    measured moves; returns G(tau) and the sector weights at beta/2 with their
-    jackknife-over-chains errors, and the run's statistics."""
+def _mc_run(hyb, I, params, window, beta, n_chains, therm, meas, n_tau, seed, precision="fp64", start=None):
+    """Chains on the semicircular bath, from empty configurations or from start (a list
+    of (cre, ann) per chain; a start whose trace vanishes is replaced by the empty
+    configuration): therm moves, then meas measured moves; returns G(tau) and the
+    sector weights at beta/2 with their jackknife-over-chains errors, and the run's
+    statistics."""
     import numpy as np
     m = hyb.Model(params, precision=precision, retain_window=window)
     delta = I.semicircle_delta(beta, 1000)
     mc = hyb.MC(m, n_chains, beta, delta, kmax=60, nmax_ops=1024, seed=seed, n_tau=n_tau)
+    if start is not None:
+        F = 2 * params.n_orb
+        r = m.trace_batch(I.from_lists([I.mc_merged(cre, ann) for cre, ann in start], beta))
+        mc.set_configs([ch if r.sign[c] != 0 else ([[]] * F, [[]] * F) for c, ch in enumerate(start)])
     t0 = time.perf_counter()
     gate = None
     if isinstance(therm, tuple):
@@ -362,8 +368,13 @@ def measure_spin_study(torch, hyb, I, j_over_u=(0.0, 0.05, 0.1, 0.15, 0.2, 0.25)
                 emin[Nb] = min(emin.get(Nb, np.inf), h.block_info(b)[2])
             h.close()
             mu = 0.5 * (emin[7] - emin[5])
-            r = _mc_run(hyb, I, I.kanamori(n, U=U, J=J, mu=mu, delta=delta), 1e-5, beta, n_chains, therm, meas,
-                        n_tau, 71)
+            p = I.kanamori(n, U=U, J=J, mu=mu, delta=delta)
+            # chains start near the equilibrium expansion order (about 200 pairs here;
+            # from empty configurations the order relaxes over ~16,000 moves)
+            setup = I.McSetup("spin", I.Workload("spin", p, beta, 0, 0.0, 0, "fp64", 1e-5), n_chains, 1000,
+                              None, 71, 240, 60, 71)
+            r = _mc_run(hyb, I, p, 1e-5, beta, n_chains, therm, meas, n_tau, 71,
+                        start=I.mc_initial_configs(setup, min_pairs=160))
             row = {"delta": dl, "J_over_U": ju, "mu": mu, "n_tr": r["n_retained"], "S2": r["S2"],
                    "S2_se": r["S2_se"], "N": r["N"], "N_se": r["N_se"], "mean_order": r["mean_order"],
                    "sign_avg": r["sign_avg"], "thermalisation": r["thermalisation"], "seconds": r["wall_s"]}
@@ -768,6 +779,7 @@ def main():
                     help="only the total-spin study: <S^2> at beta/2 for 5 orbitals, U = 2, six electrons, at "
                          "these J/U values (comma separated; 'all' for 0,0.05,0.1,0.15,0.2,0.25)")
     ap.add_argument("--spin-chains", type=int, default=128, help="chains per point of the spin study")
+    ap.add_argument("--spin-deltas", default="0,0.5", help="crystal fields of the spin study (comma separated)")
     ap.add_argument("--spin-moves", default="4000,8000",
                     help="least thermalisation moves (the gate may take up to 5x) and measured moves of the spin study")
     ap.add_argument("--seven-only", action="store_true", help="only the 7-orbital mixed workload (profiling)")
@@ -812,8 +824,9 @@ def main():
             tuple(float(x) for x in a.spin_study.split(","))
         th, me = (int(x) for x in a.spin_moves.split(","))
         th = (th, 5 * th)  # the stationarity gate: at least th, at most 5 th moves
-        print(json.dumps({"spin_study": measure_spin_study(torch, hyb, I, j_over_u=ju, n_chains=a.spin_chains,
-                                                           therm=th, meas=me)}), flush=True)
+        dl = tuple(float(x) for x in a.spin_deltas.split(","))
+        print(json.dumps({"spin_study": measure_spin_study(torch, hyb, I, j_over_u=ju, deltas=dl,
+                                                           n_chains=a.spin_chains, therm=th, meas=me)}), flush=True)
         return
     if a.comparator_only:
         print(json.dumps({"matrix_vs_krylov": measure_comparator(torch, hyb, I)}), flush=True)
@@ -823,6 +836,7 @@ def main():
         r7["roofline"] = roofline(r7, TRAFFIC.get(r7["workload"]))
         print(json.dumps({"kanamori-7orb-b40": r7}), flush=True)
         return
+    t_start = time.perf_counter()
     r5 = measure_workload(1, a.steps, a.warmup, torch, hyb, I, dump=a.dump)
     # Roofline of the dominant kernel (the path kernel, one launch per batch with the
     # tuned schedule): algorithmic bytes B_path = sum_k (2 m_k + 2) d_k s per path, i.e.
@@ -854,7 +868,7 @@ def main():
                                       "substeps", "depth_histogram", "feasible_paths", "path_bytes",
                                       "host_buffers")},
     }
-    t_leg = time.perf_counter()
+    t_leg = t_start
 
     def leg(name):
         nonlocal t_leg

@@ -298,18 +298,18 @@ def dmft_setup(n_orb: int, U: float, beta: float, n_chains: int = 128, n_delta: 
                    17 + n_orb)
 
 
-def mc_initial_configs(setup: McSetup):
+def mc_initial_configs(setup: McSetup, min_pairs: int = 0):
     """Per chain: (cre, ann) with cre[f] / ann[f] the creator / annihilator times of
     flavor f in label order (the i-th creator in time is paired with the i-th
-    annihilator).  Total pair number uniform in 0..max_init_pairs, spread over the
-    flavors uniformly; per flavor the operators alternate in time, starting with c if
-    the flavor is occupied in a reference Fock state (single occupancy, random spins)."""
+    annihilator).  Total pair number uniform in min_pairs..max_init_pairs, spread over
+    the flavors uniformly; per flavor the operators alternate in time, starting with c
+    if the flavor is occupied in a reference Fock state (single occupancy, random spins)."""
     n_orb = setup.workload.params.n_orb
     F, beta = 2 * n_orb, setup.workload.beta
     rng = np.random.default_rng(setup.init_seed)
     chains = []
     for _ in range(setup.n_chains):
-        K = int(rng.integers(0, setup.max_init_pairs + 1))
+        K = int(rng.integers(min_pairs, setup.max_init_pairs + 1))
         kf = np.bincount(rng.integers(0, F, size=K), minlength=F)
         kf = np.minimum(kf, setup.kmax_flavor)
         spins = rng.integers(0, 2, size=n_orb)
