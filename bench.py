@@ -343,6 +343,21 @@ def measure_truncation_study(torch, hyb, I, n_chains=256, n_tau=40):
     return out
 
 
+def _dominant_states(hyb, params, window=1e-5):
+    """The basis state of largest weight in each retained eigenvector (host model): Fock
+    states whose occupations start chains with a nonzero trace."""
+    import numpy as np
+    h = hyb.Model(params, precision="fp64", retain_window=window, upload=False)
+    blk, _, vec = h.retained()
+    out, off = [], 0
+    for b in blk:
+        d = h.block_info(int(b))[0]
+        out.append(h.basis_state(int(b), int(np.argmax(np.abs(vec[off:off + d])))))
+        off += d
+    h.close()
+    return sorted(set(out))
+
+
 def measure_spin_study(torch, hyb, I, j_over_u=(0.0, 0.05, 0.1, 0.15, 0.2, 0.25), deltas=(0.0, 0.5),
                        n_chains=128, therm=(4000, 20000), meas=4000, n_tau=40):
     """Sec. V.C (Fig. 7) analogue: <S^2> at beta/2 against J/U for 5 orbitals at U = 2,
@@ -370,11 +385,12 @@ def measure_spin_study(torch, hyb, I, j_over_u=(0.0, 0.05, 0.1, 0.15, 0.2, 0.25)
             mu = 0.5 * (emin[7] - emin[5])
             p = I.kanamori(n, U=U, J=J, mu=mu, delta=delta)
             # chains start near the equilibrium expansion order (about 200 pairs here;
-            # from empty configurations the order relaxes over ~16,000 moves)
+            # from empty configurations the order relaxes over ~16,000 moves), each
+            # flavor's operators alternating from a Fock state that a retained state holds
             setup = I.McSetup("spin", I.Workload("spin", p, beta, 0, 0.0, 0, "fp64", 1e-5), n_chains, 1000,
                               None, 71, 240, 60, 71)
             r = _mc_run(hyb, I, p, 1e-5, beta, n_chains, therm, meas, n_tau, 71,
-                        start=I.mc_initial_configs(setup, min_pairs=160))
+                        start=I.mc_initial_configs(setup, min_pairs=160, refs=_dominant_states(hyb, p)))
             row = {"delta": dl, "J_over_U": ju, "mu": mu, "n_tr": r["n_retained"], "S2": r["S2"],
                    "S2_se": r["S2_se"], "N": r["N"], "N_se": r["N_se"], "mean_order": r["mean_order"],
                    "sign_avg": r["sign_avg"], "thermalisation": r["thermalisation"], "seconds": r["wall_s"]}
@@ -916,5 +932,17 @@ def main():
     print(json.dumps(line), flush=True)
 
 
+def _stop_resource_tracker():
+    """The oracle's process pools (spawn) start multiprocessing's resource tracker; stop
+    it before exiting so that no helper process outlives the benchmark."""
+    try:
+        from multiprocessing import resource_tracker
+        if getattr(resource_tracker._resource_tracker, "_pid", None) is not None:
+            resource_tracker._resource_tracker._stop()
+    except Exception:
+        pass
+
+
 if __name__ == "__main__":
     main()
+    _stop_resource_tracker()

@@ -298,12 +298,13 @@ def dmft_setup(n_orb: int, U: float, beta: float, n_chains: int = 128, n_delta: 
                    17 + n_orb)
 
 
-def mc_initial_configs(setup: McSetup, min_pairs: int = 0):
+def mc_initial_configs(setup: McSetup, min_pairs: int = 0, refs=None):
     """Per chain: (cre, ann) with cre[f] / ann[f] the creator / annihilator times of
     flavor f in label order (the i-th creator in time is paired with the i-th
     annihilator).  Total pair number uniform in min_pairs..max_init_pairs, spread over
     the flavors uniformly; per flavor the operators alternate in time, starting with c
-    if the flavor is occupied in a reference Fock state (single occupancy, random spins)."""
+    if the flavor is occupied in a reference Fock state: single occupancy with random
+    spins, or one of refs (bit f set = flavor f occupied) drawn at random per chain."""
     n_orb = setup.workload.params.n_orb
     F, beta = 2 * n_orb, setup.workload.beta
     rng = np.random.default_rng(setup.init_seed)
@@ -312,10 +313,15 @@ def mc_initial_configs(setup: McSetup, min_pairs: int = 0):
         K = int(rng.integers(min_pairs, setup.max_init_pairs + 1))
         kf = np.bincount(rng.integers(0, F, size=K), minlength=F)
         kf = np.minimum(kf, setup.kmax_flavor)
-        spins = rng.integers(0, 2, size=n_orb)
         occ = np.zeros(F, dtype=bool)
-        for a in range(n_orb):
-            occ[a + n_orb * spins[a]] = True
+        if refs is None:
+            spins = rng.integers(0, 2, size=n_orb)
+            for a in range(n_orb):
+                occ[a + n_orb * spins[a]] = True
+        else:
+            s = int(refs[int(rng.integers(0, len(refs)))])
+            for f in range(F):
+                occ[f] = bool((s >> f) & 1)
         cre, ann = [], []
         for f in range(F):
             ts = np.sort(rng.uniform(0.0, beta, size=2 * kf[f]))
