@@ -125,11 +125,14 @@ def _chain_run(task):
                 accepted=accepted, min_margin=min(margins) if margins else np.inf)
 
 
-def replay_chains(params, window, table, beta, kmax, starts, seed, n_moves, n_tau, meas_every, workers=None):
+def replay_chains(params, window, table, beta, kmax, starts, seed, n_moves, n_tau, meas_every, workers=None,
+                  chain_ids=None):
     """oracle.mc.Chain replays of len(starts) chains (chain c starts from starts[c] =
     (cre, ann), or empty when that configuration has zero weight) for n_moves moves
-    with the uniforms of chain c, measuring after every meas_every-th move."""
+    with the uniforms of chain c, measuring after every meas_every-th move.  With
+    chain_ids, starts[j] is the start of chain chain_ids[j] (a sample of the chains)."""
     workers = max(1, min(workers or default_workers(), len(starts)))
-    tasks = [(c, cre, ann, seed, n_moves, n_tau, meas_every) for c, (cre, ann) in enumerate(starts)]
+    ids = list(range(len(starts))) if chain_ids is None else [int(c) for c in chain_ids]
+    tasks = [(c, cre, ann, seed, n_moves, n_tau, meas_every) for c, (cre, ann) in zip(ids, starts)]
     with _spawn_pool(workers, _chain_init, (params, window, table, beta, kmax)) as pool:
         return pool.map(_chain_run, tasks, chunksize=1)

@@ -122,6 +122,99 @@ def test_mc_five_orbital_trajectory_matches_oracle():
     assert _replay_and_compare(3, 16, 40) >= 20
 
 
+def _undetermined_on_path(o, setup, w, start, chain, n_moves, unit=2.0 ** -53, level=1e-3):
+    """Replays chain `chain` on the oracle and returns the largest u * cond over its start
+    and the nonzero proposals of its moves (cond: the first-order amplification of
+    per-propagation errors into Tr_R, TraceOracle.condition).  A value near or above one
+    means FP64 leaves that trace undetermined: any two evaluations may differ."""
+    def cond(cre, ann):
+        tau, fl, dg = MC.merged(cre, ann)
+        b = I.from_lists([(tau, fl, dg)], w.beta)
+        r = o.trace_batch(b)
+        return 0.0 if r.sign[0] == 0 else float(o.condition(b, r)[0])
+    worst = 0.0
+    try:
+        ch = MC.Chain(o, setup.delta, w.beta, start[0], start[1], setup.kmax_flavor)
+    except ValueError:
+        return 0.0
+    worst = max(worst, unit * cond(ch.cre, ch.ann))
+    for step in range(n_moves):
+        u = MC.move_uniforms(setup.seed, chain, step)
+        kind, cre2, ann2, s, _, _ = ch.propose(u)
+        if kind and s != 0:
+            worst = max(worst, unit * cond(cre2, ann2))
+        ch.step(u)
+    return worst
+
+
+def test_mc_benchmark_chains_sampled_against_oracle():
+    """The benchmark's Monte Carlo workload at its size: 256 five-orbital chains started
+    at total pair numbers uniform in 0..200.  All of them run on the device; 32 chains
+    drawn by a seeded sample are replayed by the oracle move by move (same uniforms:
+    chain c draws with its own counter), and their configurations, signs, log-weights,
+    inverses M and G(tau) accumulators must agree after 8 moves.
+
+    The starting configurations pair each flavor's operators from a random spin pattern,
+    and some of them hold paths through excited spin states over long intervals: their
+    traces have cut-point condition numbers up to 1e19, beyond what FP64 determines
+    (rounding noise in lower-lying states of the same block outgrows the exact value),
+    and any two FP64 evaluations of them differ.  A sampled chain that ends apart from
+    the oracle's must have met such a trace (u * cond >= 1e-3 at its start or at one of
+    its proposals), and at least 24 of the 32 must agree exactly."""
+    _require_gpu()
+    setup = I.mc_setup(3)
+    w = setup.workload
+    F = 2 * w.params.n_orb
+    kmax, n_moves, n_tau, meas_every = setup.kmax_flavor, 8, 20, 2
+    m = hyb.model_for_workload(w)
+    mc = hyb.MC(m, setup.n_chains, w.beta, setup.delta, kmax=kmax, nmax_ops=512, seed=setup.seed, n_tau=n_tau,
+                meas_every=meas_every)
+    starts = list(I.mc_initial_configs(setup))
+    ids = I.parity_sample(setup.n_chains, 32, 29)
+    reps = OP.replay_chains(w.params, w.retain_window, setup.delta, w.beta, kmax, [starts[c] for c in ids],
+                            setup.seed, n_moves, n_tau, meas_every, chain_ids=ids)
+    # every chain starts as the oracle decided for the sampled ones (a zero-weight start
+    # becomes empty); the unsampled chains start where their traces are nonzero
+    r0 = m.trace_batch(I.from_lists([I.mc_merged(cre, ann) for cre, ann in starts], w.beta))
+    init = [ch if r0.sign[c] != 0 else ([[]] * F, [[]] * F) for c, ch in enumerate(starts)]
+    for j, c in enumerate(ids):
+        init[c] = (reps[j]["start"][0], reps[j]["start"][1])
+    mc.set_configs(init)
+    mc.sweep(n_moves)
+    st = mc.state(with_M=True)
+    g, ms, nm = mc.accumulators()
+    o = T.build(w.params, w.retain_window)
+    worst_M = worst_w = 0.0
+    agree, apart = 0, []
+    for j, c in enumerate(ids):
+        r = reps[j]
+        same = st["sign"][c] == r["sign"] and r["min_margin"] > 1e-8
+        for f in range(F):
+            k = len(r["cre"][f])
+            same = same and st["k"][c, f] == k and list(st["cre"][c, f, :k]) == r["cre"][f] \
+                and list(st["ann"][c, f, :k]) == r["ann"][f]
+        if same and abs(st["logw"][c] - r["logw"]) <= 1e-10:
+            agree += 1
+            for f in range(F):
+                k = len(r["cre"][f])
+                if k:
+                    Mi = np.linalg.inv(MC.hyb_matrix(setup.delta, w.beta, r["cre"][f], r["ann"][f]))
+                    worst_M = max(worst_M, np.max(np.abs(st["M"][c, f, :k, :k] - Mi)) / np.max(np.abs(Mi)))
+            worst_w = max(worst_w, abs(st["logw"][c] - r["logw"]))
+            assert np.max(np.abs(g[c] - r["acc"])) <= 1e-9 * max(1e-300, np.max(np.abs(r["acc"])))
+            continue
+        # apart: the oracle's own path must hold an undetermined trace
+        und = _undetermined_on_path(o, setup, w, starts[c], int(c), n_moves)
+        assert und >= 1e-3, (int(c), und)
+        apart.append((int(c), und))
+    assert worst_M <= 1e-10 and worst_w <= 1e-10, (worst_M, worst_w)
+    assert agree >= 24, (agree, apart)
+    print(f"256 chains, 32 replayed by the oracle over {n_moves} moves: {agree} agree exactly; apart (each with an "
+          f"FP64-undetermined trace, u * cond): {[(c, f'{x:.0e}') for c, x in apart]}; mean order "
+          f"{st['k'].sum(axis=1).mean():.1f} pairs; M {worst_M:.1e}, logw {worst_w:.1e}")
+    mc.close()
+
+
 def test_mc_capacity_limits_match_oracle():
     """A pair capacity of 2 per flavor: insertions beyond it are impossible moves on
     both sides."""
