@@ -145,11 +145,20 @@ def _log(msg):
 
 
 def lib():
-    """Loads libhyb.so (raises if it was not built)."""
+    """Loads libhyb.so (raises if it was not built).
+
+    torch, when importable, is loaded first: its HIP runtime and rocBLAS carry the same
+    sonames as the ones libhyb links, so libhyb then binds to torch's copies and the two
+    share one HIP runtime (device pointers and streams pass between them, and the
+    device is seen the same way by both)."""
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: run paper_0908_0681_amd.build first")
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         for name, (res, args) in _SIGS.items():
             f = getattr(L, name)
