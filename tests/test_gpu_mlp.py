@@ -263,7 +263,7 @@ def _edge_distance(z, u):
     return float(np.min(np.abs(c[:-1] - u * c[-1])) / c[-1])
 
 
-@pytest.mark.parametrize("which,n_chains,n_moves", [(6, 8, 120), (3, 3, 10)])
+@pytest.mark.parametrize("which,n_chains,n_moves", [(6, 8, 120), (3, 16, 30)])
 def test_mc_learned_trajectory_matches_oracle(which, n_chains, n_moves):
     """Learned moves replayed move by move: the oracle chain with the same network
     (FP64 with BF16 rounding points) and the same counter-based uniforms against the
