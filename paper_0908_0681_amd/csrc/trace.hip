@@ -174,8 +174,8 @@ struct Variant {
    reinterpret_cast<const void*>(&k_path_chunk<VT, NT, RPT, MAXM, MF, VL, OCC>)}
 
 static const Variant kVariants[] = {
-    VARIANT(double, 64, 1, 12, false, false, 1, "f64_nt64_r1_m12"),
-    VARIANT(double, 64, 2, 12, false, false, 1, "f64_nt64_r2_m12"),
+    VARIANT(double, 64, 1, 12, false, false, 2, "f64_nt64_r1_m12"),
+    VARIANT(double, 64, 2, 12, false, false, 2, "f64_nt64_r2_m12"),
     VARIANT(double, 64, 2, 16, false, false, 1, "f64_nt64_r2_m16"),
     VARIANT(double, 128, 1, 12, false, false, 1, "f64_nt128_r1_m12"),
     VARIANT(double, 128, 4, 12, false, false, 1, "f64_nt128_r4_m12"),
@@ -185,13 +185,13 @@ static const Variant kVariants[] = {
     VARIANT(float, 256, 5, 12, false, false, 1, "f32_nt256_r5_m12"),
     VARIANT(float, 256, 5, 16, false, false, 1, "f32_nt256_r5_m16"),
     VARIANT(float, 512, 3, 12, false, false, 1, "f32_nt512_r3_m12"),
-    VARIANT(double, 64, 2, 12, true, false, 1, "f64_nt64_r2_m12_mf"),
+    VARIANT(double, 64, 2, 12, true, false, 2, "f64_nt64_r2_m12_mf"),
     VARIANT(double, 256, 5, 12, true, false, 1, "f64_nt256_r5_m12_mf"),
     VARIANT(float, 64, 2, 12, true, false, 1, "f32_nt64_r2_m12_mf"),
     VARIANT(float, 256, 5, 12, true, false, 1, "f32_nt256_r5_m12_mf"),
     VARIANT(float, 64, 20, 8, false, true, 1, "f32_nt64_r20_m8_vl"),
     VARIANT(float, 64, 20, 8, true, true, 1, "f32_nt64_r20_m8_vl_mf"),
-    VARIANT(double, 64, 2, 12, false, true, 1, "f64_nt64_r2_m12_vl"),
+    VARIANT(double, 64, 2, 12, false, true, 2, "f64_nt64_r2_m12_vl"),
 };
 static const int kNumVariants = int(sizeof(kVariants) / sizeof(kVariants[0]));
 

@@ -243,14 +243,21 @@ struct PathEngine {
   static constexpr int SLAB_BYTES = (MF || (NT == 64 && RPT > 4)) ? 0
                                     : (NT >= 512) ? 64 * 1024 : (NT >= 256) ? 96 * 1024 : 10 * 1024 * (NT / 64);
   static constexpr int KL0 = SLAB_BYTES / (NR * int(sizeof(VT) + sizeof(int16_t)));
-  static constexpr int KL = KL0 > 16 ? 16 : KL0;
+  // Slots are staged in chunks of CH (16 bytes of values, 2 doubles or 4 floats):
+  // chunk c of local row r holds the row's slots c*CH .. c*CH+CH-1, so that one
+  // 16-byte LDS read brings CH values and one 4- or 8-byte read their columns.
+  static constexpr int CH = 16 / int(sizeof(VT));
+  static constexpr int KL = (KL0 > 16 ? 16 : KL0) / CH * CH;
+  static constexpr int NCH = KL / CH;  // chunks per row
+  using VV = std::conditional_t<sizeof(VT) == 8, double2, float4>;   // CH values
+  using CV = std::conditional_t<sizeof(VT) == 8, uint32_t, uint2>;   // CH int16 columns
   struct Smem {
     VT vec[VL ? 1 : NT * RPT];
     VT vb[VL ? (MAXM + 1) * NT * RPT : 1];  // the Krylov basis when VL
     double red[2][NW][NRED];
     Small small[NW];
-    VT sval[KL > 0 ? KL * NR : 1];       // slot q of local row r at q * NR + r
-    int16_t scol[KL > 0 ? KL * NR : 1];
+    VV sval[NCH > 0 ? NCH * NR : 1];     // chunk c of local row r at c * NR + r
+    CV scol[NCH > 0 ? NCH * NR : 1];
     int16_t rh[MF ? 128 : 1];            // matrix-free: rank_half of the model (2^n_orb <= 128)
   };
 
@@ -301,15 +308,19 @@ struct PathEngine {
           if (k < kact) S.red[rbuf][wid][k] = v[k];
       }
       __syncthreads();
+      // lane k adds the waves' partials of value k (all loads in flight at once),
+      // then every lane reads the totals from those lanes
+      double s = 0.0;
+      if (lane < kact) {
+        double part[NW];
 #pragma unroll
-      for (int k = 0; k < K; ++k) {
-        if (k < kact) {
-          double s = 0.0;
+        for (int w = 0; w < NW; ++w) part[w] = S.red[rbuf][w][lane];
 #pragma unroll
-          for (int w = 0; w < NW; ++w) s += S.red[rbuf][w][k];
-          v[k] = s;
-        }
+        for (int w = 0; w < NW; ++w) s += part[w];
       }
+#pragma unroll
+      for (int k = 0; k < K; ++k)
+        if (k < kact) v[k] = readlane_d(s, k);
       rbuf ^= 1;
     }
   }
@@ -399,11 +410,56 @@ struct PathEngine {
           y[k] = static_cast<VT>(dg[k] * to_d(x[k]) + row_free(B, rstate[k], xs));
           continue;
         }
-        if (staged) {
-          const int K = P.ek;
-#pragma unroll 2
-          for (int q = 0; q < K; ++q) acc += S.sval[q * NR + r] * xs[S.scol[q * NR + r]];
-        } else if constexpr (KL == 0) {
+        if constexpr (NCH > 0) {
+          if (staged) {
+            // The columns and values of up to G chunks are requested together, then
+            // all of their gathers, so a row costs two LDS round trips rather than
+            // one per slot.  Chunks past the row's last are re-read (clamped) with
+            // their values taken as 0; slots are summed in slot order.
+            constexpr int G = NCH < 4 ? NCH : 4;
+            const int nch = (P.ek + CH - 1) / CH;
+            for (int c0 = 0; c0 < nch; c0 += G) {
+              CV cw[G];
+              VV vw[G];
+#pragma unroll
+              for (int g = 0; g < G; ++g) {
+                const bool real = c0 + g < nch;
+                const int c = real ? c0 + g : nch - 1;
+                cw[g] = S.scol[c * NR + r];
+                vw[g] = S.sval[c * NR + r];
+                if (!real) vw[g] = VV{};
+              }
+              VT xg[G][CH];
+#pragma unroll
+              for (int g = 0; g < G; ++g) {
+                if constexpr (CH == 2) {
+                  xg[g][0] = xs[cw[g] & 0xffffu];
+                  xg[g][1] = xs[cw[g] >> 16];
+                } else {
+                  xg[g][0] = xs[cw[g].x & 0xffffu];
+                  xg[g][1] = xs[cw[g].x >> 16];
+                  xg[g][2] = xs[cw[g].y & 0xffffu];
+                  xg[g][3] = xs[cw[g].y >> 16];
+                }
+              }
+#pragma unroll
+              for (int g = 0; g < G; ++g) {
+                if constexpr (CH == 2) {
+                  acc += vw[g].x * xg[g][0];
+                  acc += vw[g].y * xg[g][1];
+                } else {
+                  acc += vw[g].x * xg[g][0];
+                  acc += vw[g].y * xg[g][1];
+                  acc += vw[g].z * xg[g][2];
+                  acc += vw[g].w * xg[g][3];
+                }
+              }
+            }
+            y[k] = static_cast<VT>(dg[k] * to_d(x[k]) + to_d(acc));
+            continue;
+          }
+        }
+        if constexpr (KL == 0) {
           // the block's natural-order ELL rows straight from global memory (L2): slot q
           // of row r at state_off * K + q * dim + r, so a wave's loads are contiguous
           const int K = P.ek;
@@ -434,7 +490,8 @@ struct PathEngine {
   // by this thread, so no barrier is needed).  Returns whether the slots are staged.
   __device__ __forceinline__ bool stage_rows(const BlockDev& B, double (&dg)[RPT]) {
     const int K = P.ek;
-    const bool staged = K <= KL;
+    const int nch = (K + CH - 1) / CH;
+    const bool staged = nch <= NCH;
     const int64_t base = int64_t(B.state_off) * K;
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
@@ -455,11 +512,11 @@ struct PathEngine {
     for (int k = 0; k < RPT; ++k) {
       const int r = row(k);
       const bool in = r < B.dim;
-      if constexpr (KL > 0) {
+      if constexpr (NCH > 0) {
         if (staged && in && K > 0) {
           // every slot of the row is requested before the first LDS store (slots past
-          // K re-read slot K - 1 of the same row and are not stored), so the loads
-          // are in flight together
+          // K re-read slot K - 1 of the same row), so the loads are in flight
+          // together; the last chunk is padded with value 0 at column 0
           VT vv[KL];
           int16_t cc[KL];
 #pragma unroll
@@ -471,10 +528,28 @@ struct PathEngine {
           }
 #pragma unroll
           for (int q = 0; q < KL; ++q)
-            if (q < K) {
-              S.sval[q * NR + r] = vv[q];
-              S.scol[q * NR + r] = cc[q];
+            if (q >= K) {
+              vv[q] = VT(0);
+              cc[q] = 0;
             }
+#pragma unroll
+          for (int c = 0; c < NCH; ++c) {
+            if (c < nch) {
+              const int q = c * CH;
+              VV v;
+              CV w;
+              if constexpr (CH == 2) {
+                v = VV{vv[q], vv[q + 1]};
+                w = uint32_t(uint16_t(cc[q])) | (uint32_t(uint16_t(cc[q + 1])) << 16);
+              } else {
+                v = VV{vv[q], vv[q + 1], vv[q + 2], vv[q + 3]};
+                w = CV{uint32_t(uint16_t(cc[q])) | (uint32_t(uint16_t(cc[q + 1])) << 16),
+                       uint32_t(uint16_t(cc[q + 2])) | (uint32_t(uint16_t(cc[q + 3])) << 16)};
+              }
+              S.sval[c * NR + r] = v;
+              S.scol[c * NR + r] = w;
+            }
+          }
         }
       }
     }
@@ -589,6 +664,17 @@ struct PathEngine {
     const int G = (m <= 8) ? 8 : 4;
     const int k = lane / G, sub = lane - (lane / G) * G;
     const bool act = k < m;
+    // this lane's poles (i = sub, sub + G, ...) and squared couplings in registers,
+    // so that the iterations below read no LDS
+    constexpr int NPL = (NP + 3) / 4;
+    double pth[NPL], pzz[NPL];
+#pragma unroll
+    for (int t = 0; t < NPL; ++t) {
+      const int i = sub + t * G;
+      const int ic = i < n ? i : 0;
+      pth[t] = W.tz[2 * ic];
+      pzz[t] = W.tz[2 * ic + 1];
+    }
     auto gsum = [&](double v) {
       v += dpp_d<0xB1>(v);                 // lane ^ 1
       v += dpp_d<0x4E>(v);                 // lane ^ 2
@@ -599,13 +685,17 @@ struct PathEngine {
     // at lam = tho + x; sabs = sum of |z_i^2 / (theta_i - lam)|
     auto eval = [&](double tho, double x, double& dl_sum, double& dr_sum, double& sabs) {
       double sum = 0.0, dl = 0.0, dr = 0.0, sa = 0.0;
-      for (int i = sub; i < n; i += G) {
-        const double r = rcp_d((W.tz[2 * i] - tho) - x);
-        const double ti = W.tz[2 * i + 1] * r;
-        sum += ti;
-        if (i < k) dl += ti * r;
-        else dr += ti * r;
-        sa += fabs(ti);
+#pragma unroll
+      for (int t = 0; t < NPL; ++t) {
+        const int i = sub + t * G;
+        if (i < n) {
+          const double r = rcp_d((pth[t] - tho) - x);
+          const double ti = pzz[t] * r;
+          sum += ti;
+          if (i < k) dl += ti * r;
+          else dr += ti * r;
+          sa += fabs(ti);
+        }
       }
       sum = gsum(sum);
       dl_sum = gsum(dl);
@@ -651,9 +741,13 @@ struct PathEngine {
     // lam = theta_o
     {
       double a = 0.0, zp = 0.0;
-      for (int i = sub; i < n; i += G) {
-        zp += W.tz[2 * i + 1];
-        if (i != o) a += W.tz[2 * i + 1] * rcp_d(W.tz[2 * i] - tho);
+#pragma unroll
+      for (int t = 0; t < NPL; ++t) {
+        const int i = sub + t * G;
+        if (i < n) {
+          zp += pzz[t];
+          if (i != o) a += pzz[t] * rcp_d(pth[t] - tho);
+        }
       }
       a = gsum(a);
       const double zn = sqrt(gsum(zp));
@@ -755,16 +849,22 @@ struct PathEngine {
     if (lane < n) {
       const int i = lane;
       const double ti = W.tz[2 * i];
-      double f[MAXM];
+      // every operand is requested before the first product (entries at and past m
+      // are read but not used)
+      double f[MAXM], dn[MAXM];
 #pragma unroll
       for (int j = 0; j < MAXM; ++j) {
-        f[j] = 1.0;
+        // denominator pole of factor j: theta_j left of i, theta_{j-1} right of i+1
+        const int pj = (j < i) ? j : (j > 0 ? j - 1 : 0);
+        dn[j] = W.tz[2 * pj];
+        f[j] = (W.tho[j] - ti) + W.xr[j];
+      }
+#pragma unroll
+      for (int j = 0; j < MAXM; ++j) {
         if (j < m) {
-          const double dj = (W.tho[j] - ti) + W.xr[j];
-          // denominator pole of factor j: theta_j left of i, theta_{j-1} right of i+1
-          if (j < i) f[j] = dj * rcp_d(W.tz[2 * j] - ti);
-          else if (j > i + 1) f[j] = dj * rcp_d(W.tz[2 * (j - 1)] - ti);
-          else f[j] = dj;
+          if (j < i || j > i + 1) f[j] *= rcp_d(dn[j] - ti);
+        } else {
+          f[j] = 1.0;
         }
       }
 #pragma unroll
@@ -781,20 +881,26 @@ struct PathEngine {
     // eigenvector k of the arrowhead into column k of U
     bool oku = true;
     if (lane < m) {
+      const double thl = W.tho[lane], xrl = W.xr[lane];
+      double uv[NP], tv[NP];
+#pragma unroll
+      for (int i = 0; i < NP; ++i) {
+        uv[i] = W.zh[i];
+        tv[i] = W.tz[2 * i];
+      }
       double nrm = 1.0;
 #pragma unroll
       for (int i = 0; i < NP; ++i) {
         if (i < n) {
-          const double ui = W.zh[i] * rcp_d((W.tho[lane] - W.tz[2 * i]) + W.xr[lane]);
-          W.u[i * QLD + lane] = ui;
-          nrm += ui * ui;
+          uv[i] *= rcp_d((thl - tv[i]) + xrl);
+          nrm += uv[i] * uv[i];
         }
       }
       oku = (nrm < 1e300);
       const double inv = rcp_d(sqrt(nrm));
 #pragma unroll
       for (int i = 0; i < NP; ++i)
-        if (i < n) W.u[i * QLD + lane] *= inv;
+        if (i < n) W.u[i * QLD + lane] = uv[i] * inv;
       W.u[n * QLD + lane] = inv;
     }
     if (wave_any(!oku)) return false;
@@ -807,10 +913,16 @@ struct PathEngine {
       if (r < m && j < m) {
         double acc;
         if (r < n) {
+          double qv[NP], uv[NP];
+#pragma unroll
+          for (int i = 0; i < NP; ++i) {
+            qv[i] = Q[r * QLD + i];
+            uv[i] = W.u[i * QLD + j];
+          }
           acc = 0.0;
 #pragma unroll
           for (int i = 0; i < NP; ++i)
-            if (i < n) acc += Q[r * QLD + i] * W.u[i * QLD + j];
+            if (i < n) acc += qv[i] * uv[i];
         } else {
           acc = W.u[n * QLD + j];
         }
@@ -1088,8 +1200,17 @@ struct PathEngine {
           // y = Q w: lane r (<= j) gets component r
           if (lane <= j) W.wk[lane] = wl;
           wave_sync();
+          const int rr = lane <= j ? lane : 0;
+          double qv[MAXM], wv[MAXM];
+#pragma unroll
+          for (int i = 0; i < MAXM; ++i) {
+            qv[i] = Q[rr * QLD + i];
+            wv[i] = W.wk[i];
+          }
           double yr = 0.0;
-          for (int i = 0; i <= j; ++i) yr += Q[(lane <= j ? lane : 0) * QLD + i] * W.wk[i];
+#pragma unroll
+          for (int i = 0; i < MAXM; ++i)
+            if (i <= j) yr += qv[i] * wv[i];
           m = j + 1;
           tau_used = tau_try;
           yv = (lane <= j) ? yr : 0.0;
