@@ -39,7 +39,7 @@ struct DeviceModel {
   // with their own index and 0
   int16_t* ell_col = nullptr;
   float* ell_val32 = nullptr;
-  int16_t* ell_perm = nullptr;  // [dim_b] per block: rows by descending length (ELL row i is row perm[i])
+  int16_t* ell_perm = nullptr;  // [dim_b] per block: row pairs by descending length (ELL row i is row perm[i])
   int16_t* ell_len = nullptr;   // [dim_b] per block: length of ELL row i
   // the same rows in natural order for the trace kernels, every block padded to the
   // model-wide slot count tell_k: slot k of row r of block b at

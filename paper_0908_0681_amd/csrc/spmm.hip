@@ -28,8 +28,10 @@ constexpr int SPMM_PF = (SPMM_MAXDIM * 4 + SPMM_NT - 1) / SPMM_NT;  // float4 st
 constexpr int SPMM_KCH = 4;                        // ELL slots loaded together
 static_assert(SPMM_PF * SPMM_NT == SPMM_MAXDIM * 4, "staging covers the LDS panel exactly");
 
-// The matrix is read in the block's padded ELL form with rows sorted by length
-// (slot k of ELL row i at k * dim + i, ELL row i = row perm[i]).  Each lane owns a row and all 16 vectors of the panel: a slot
+// The matrix is read in the block's padded ELL form with the row pairs (2q, 2q + 1)
+// kept together and sorted by length (slot k of ELL row i at k * dim + i, ELL row i =
+// row perm[i]), so two neighbouring lanes write the two 64-byte halves of one
+// 128-byte line of Y.  Each lane owns a row and all 16 vectors of the panel: a slot
 // costs one column and one value load (coalesced across the wavefront's rows),
 // four 16-byte LDS reads of the referenced row and 16 FMAs; the row of Y leaves
 // as four 16-byte stores.
@@ -67,7 +69,7 @@ __global__ __launch_bounds__(SPMM_NT) void k_spmm16(int dim, int state_off, int 
     // all reading chunk h of different rows at once.
     const int rot = tid & 3;
     for (int i = tid; i < dim; i += SPMM_NT) {
-      // ELL rows are sorted by length, so the rows of a wavefront need about the
+      // ELL rows are sorted by pair length, so the rows of a wavefront need about the
       // same number of slots; each lane stops at its own row's length
       const int r = eperm[i];
       const int n = elen[i];

@@ -495,8 +495,11 @@ int hyb_model_upload(hyb_model* m, void* stream) {
     }
   std::vector<float> val32(m->val.begin(), m->val.end());
   std::vector<float> rv32(m->ret_vec.begin(), m->ret_vec.end());
-  // ELL copy of each block's off-diagonal rows, rows sorted by descending length
-  // (stable): ELL row i is row perm[i] of the block, slot k of ELL row i at
+  // ELL copy of each block's off-diagonal rows for the block SpMM: the row pairs
+  // (2q, 2q + 1), which share a 128-byte line of a 16-vector panel, are kept together
+  // and sorted by their longer row, descending (stable), so that a wavefront's rows
+  // need about the same number of slots and each line of Y is written whole by two
+  // neighbouring lanes.  ELL row i is row perm[i] of the block, slot k of ELL row i at
   // off + k * dim + i; short rows are padded with their own index and 0
   m->ell_k.assign(m->n_blocks, 0);
   m->ell_off.assign(m->n_blocks, 0);
@@ -515,10 +518,21 @@ int hyb_model_upload(hyb_model* m, void* stream) {
   std::vector<int16_t> ell_perm(std::max<int64_t>(m->n_states, 1)), ell_len(std::max<int64_t>(m->n_states, 1));
   for (int b = 0; b < m->n_blocks; ++b) {
     const BlockDev& B = m->blocks[b];
-    std::vector<int> order(B.dim);
-    for (int r = 0; r < B.dim; ++r) order[r] = r;
     auto len = [&](int r) { return m->rowptr[B.state_off + r + 1] - m->rowptr[B.state_off + r]; };
-    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return len(x) > len(y); });
+    // whole pairs first (so every pair starts at an even ELL row), the odd last row
+    // of an odd-dimensional block after them
+    std::vector<int> pairs(B.dim / 2);
+    for (int q = 0; q < int(pairs.size()); ++q) pairs[q] = q;
+    std::stable_sort(pairs.begin(), pairs.end(), [&](int x, int y) {
+      return std::max(len(2 * x), len(2 * x + 1)) > std::max(len(2 * y), len(2 * y + 1));
+    });
+    std::vector<int> order;
+    order.reserve(B.dim);
+    for (int q : pairs) {
+      order.push_back(2 * q);
+      order.push_back(2 * q + 1);
+    }
+    if (B.dim % 2) order.push_back(B.dim - 1);
     for (int i = 0; i < B.dim; ++i) {
       const int r = order[i];
       const int g = B.state_off + r;
