@@ -56,12 +56,13 @@ __global__ __launch_bounds__(NT, OCC) void k_path_prop(TraceParams P, int k) {
 }
 
 // Operators [k0, k1) of every path, one workgroup per path: the propagation before
-// operator k (k > 0) and the operator itself, exactly as the single-step kernels,
-// separated by workgroup barriers (the path's vector passes through global memory).
+// operator k (k > 0) and the operator itself, with the same arithmetic as the
+// single-step kernels; the path's state stays on chip between operators.
 template <typename VT, int NT, int RPT, int MAXM, bool MF, bool VL, int OCC>
 __global__ __launch_bounds__(NT, OCC) void k_path_chunk(TraceParams P, int k0, int k1) {
   __shared__ typename PathEngine<VT, NT, RPT, MAXM, MF, VL>::Smem S;
   __shared__ double red[NT / 64];
+  __shared__ PathCarry carry;
   const int w = blockIdx.x;
   if (w >= P.counters[0]) return;
   {
@@ -70,14 +71,7 @@ __global__ __launch_bounds__(NT, OCC) void k_path_chunk(TraceParams P, int k0, i
     const int64_t n = cfg_end(P, c) - P.offsets[c];
     if (int64_t(k1) > n) k1 = int(n);
   }
-  for (int k = k0; k < k1; ++k) {
-    if (k > 0) {
-      path_prop<VT, NT, RPT, MAXM, MF, VL>(P, w, k, S);
-      __syncthreads();
-    }
-    path_op<VT, NT, RPT>(P, w, k, red);
-    __syncthreads();
-  }
+  path_run<VT, NT, RPT, MAXM, MF, VL>(P, w, k0, k1, S, red, carry);
 }
 
 template <typename VT, int NT, int RPT>

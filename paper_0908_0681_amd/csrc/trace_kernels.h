@@ -1476,6 +1476,143 @@ __device__ inline void path_prop(const TraceParams& P, int w, int k,
   }
 }
 
+// Running totals of one path between its first and last operator (kept in LDS by
+// thread 0, so that they hold no registers during the propagations).
+struct PathCarry {
+  double ell;
+  int64_t rowsteps, rows;
+  int32_t steps, subs;
+};
+
+// Steps 4-5 for operators [k0, k1) of one path, fused: the same arithmetic as
+// path_prop / path_op in the same order, with the vector in registers, the totals
+// in LDS and the operator's gather reading the vector from LDS, so that only the
+// first and the last operator touch the path's global state.  k1 must not exceed
+// the configuration's operator count.
+template <typename VT, int NT, int RPT, int MAXM, bool MF, bool VL>
+__device__ inline void path_run(const TraceParams& P, int w, int k0, int k1,
+                                typename PathEngine<VT, NT, RPT, MAXM, MF, VL>::Smem& S, double* red,
+                                PathCarry& pc) {
+  using E = PathEngine<VT, NT, RPT, MAXM, MF, VL>;
+  if (k0 >= k1 || P.st_status[w] != PATH_ACTIVE) return;
+  const int id = P.work[w];
+  const int c = id / P.n_ret;
+  const int64_t o0 = P.offsets[c];
+  E eng(P, S);
+  int status = PATH_ACTIVE;
+  int blk = P.st_block[w];
+  if (threadIdx.x == 0) {
+    pc.ell = P.st_ell[w];
+    pc.steps = P.st_steps[w];
+    pc.subs = P.st_subs[w];
+    pc.rowsteps = P.st_rowsteps[w];
+    pc.rows = P.st_rows[w];
+  }
+  VT x[RPT];
+  {
+    const int dim = P.blocks[blk].dim;
+    const VT* vec = path_vec<VT>(P, k0 & 1, w);
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int r = eng.row(q);
+      x[q] = (r < dim) ? vec[r] : VT(0);
+    }
+  }
+  // the vector in LDS for the operator's gather (VL engines keep no separate copy)
+  VT* xs = VL ? S.vb : S.vec;
+  int k = k0;
+  for (; k < k1; ++k) {
+    if (k > 0) {
+      const BlockDev B = P.blocks[blk];
+      double ell = 0.0;
+      int steps = 0, subs = 0;
+      eng.work = 0;
+      eng.nops_budget = 1;
+      const bool ok = eng.propagate(B, P.tau[o0 + k] - P.tau[o0 + k - 1], x, ell, steps, subs);
+      if (threadIdx.x == 0) {
+        pc.ell += ell;
+        pc.steps += steps;
+        pc.subs += subs;
+        pc.rowsteps += int64_t(steps) * B.dim;
+        pc.rows += B.dim;
+      }
+      if (!ok) {
+        status = PATH_FAILED;
+        break;
+      }
+    }
+    // operator k: signed gather from the source block into the target block
+    const int f = P.flavor[o0 + k];
+    const int dg = P.dagger[o0 + k] ? 1 : 0;
+    const BlockDev B = P.blocks[blk];
+    int nu = B.n_up, nd = B.n_dn;
+    if (f < P.n_orb) nu += dg ? 1 : -1; else nd += dg ? 1 : -1;
+    if (nu < 0 || nu > P.n_orb || nd < 0 || nd > P.n_orb) {  // excluded by the scan
+      status = PATH_FAILED;
+      break;
+    }
+    const int bt = nd * (P.n_orb + 1) + nu;
+    const BlockDev Bt = P.blocks[bt];
+    __syncthreads();  // the propagation's last LDS reads are done
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int r = eng.row(q);
+      if (r < B.dim) xs[r] = x[q];
+    }
+    __syncthreads();
+    VT val[RPT];
+    double part = 0.0;
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int r = eng.row(q);
+      const VT v = (r < Bt.dim) ? gather_op<VT>(P.states, P.rank, Bt, r, f, dg, xs) : VT(0);
+      val[q] = v;
+      part += to_d(v) * to_d(v);
+    }
+    part = wave_sum(part);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = part;
+    __syncthreads();
+    double n2 = 0.0;
+#pragma unroll
+    for (int q = 0; q < NT / 64; ++q) n2 += red[q];
+    __syncthreads();  // red and xs are rewritten by the next operator / propagation
+    // a unit vector mapped to (almost) nothing: a zero imposed by symmetry
+    if (!(n2 > P.zero_tol2) || !isfinite(n2)) {
+      const bool zero = (n2 >= 0.0) && (n2 <= P.zero_tol2);
+      status = zero ? PATH_ZERO : PATH_FAILED;
+      if (!zero && threadIdx.x == 0) atomicOr(&P.counters[2], ERR_NONFINITE);
+      break;
+    }
+    const double inv = 1.0 / sqrt(n2);
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int r = eng.row(q);
+      x[q] = (r < Bt.dim) ? static_cast<VT>(to_d(val[q]) * inv) : VT(0);
+    }
+    blk = bt;
+    if (threadIdx.x == 0) pc.ell += 0.5 * log(n2);
+  }
+  if (status == PATH_ACTIVE) {
+    // operators [k0, k1) applied: the vector goes where operator k1 - 1 leaves it
+    const int dim = P.blocks[blk].dim;
+    VT* vec = path_vec<VT>(P, k1 & 1, w);
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int r = eng.row(q);
+      if (r < dim) vec[r] = x[q];
+    }
+  }
+  if (threadIdx.x == 0) {
+    P.st_status[w] = status;
+    P.st_block[w] = blk;
+    P.st_ell[w] = pc.ell;
+    P.st_steps[w] = pc.steps;
+    P.st_subs[w] = pc.subs;
+    P.st_rowsteps[w] = pc.rowsteps;
+    P.st_rows[w] = pc.rows;
+  }
+}
+
 // Step 7: overlap with <E_i| closes the path; writes the per-path sign / log.
 template <typename VT, int NT, int RPT>
 __device__ inline void path_final(const TraceParams& P, int w, double* red) {
