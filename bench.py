@@ -28,7 +28,7 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch of the path kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE,
 # scaled by the same counters on a plain 1 GiB device copy (FETCH_SIZE x2.0,
 # WRITE_SIZE x1.0); None once the kernel changes after the counters were taken.
-TRAFFIC = {"kanamori-5orb-b50": 25_160_768.0, "kanamori-7orb-b40": 138_759_821.0}
+TRAFFIC = {"kanamori-5orb-b50": 27_810_432.0, "kanamori-7orb-b40": 26_644_387.2}
 
 
 def device_batch(batch, torch):
@@ -408,7 +408,8 @@ def measure_spmm(torch, hyb, I, n_vec=262144, reps=10):
     the pass streams HBM.  Algorithmic bytes: 2 d N_v 4 (read X, write Y) plus the
     block's CSR (values, columns, row pointers, FP64 diagonal).  A plain device
     copy of the same size is timed alongside; N_v = 8192 (cache-resident, 40 MB) is
-    reported as an effective bandwidth."""
+    reported as an effective bandwidth.  Ten untimed passes come first: the first
+    passes over freshly allocated gigabyte buffers run up to 15% slower."""
     w = I.workload(2)
     m = hyb.model_for_workload(w)
     n_orb = w.params.n_orb
@@ -418,7 +419,7 @@ def measure_spmm(torch, hyb, I, n_vec=262144, reps=10):
     for nv, label in ((n_vec, "hbm"), (8192, "cache_resident")):
         X = torch.randn(nv // 16, dim, 16, device="cuda", dtype=torch.float32)
         Y = torch.empty_like(X)
-        for _ in range(2):
+        for _ in range(10):
             m.block_spmm(b, X, Y, nv)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -432,7 +433,7 @@ def measure_spmm(torch, hyb, I, n_vec=262144, reps=10):
         out[label] = {"n_vec": nv, "ms": ms, "bytes": byts, "GBps": byts / (ms / 1e3) / 1e9,
                       "frac": byts / (ms / 1e3) / 1e9 / HBM_PEAK_GBS}
         if label == "hbm":
-            for _ in range(2):
+            for _ in range(10):
                 Y.copy_(X)
             torch.cuda.synchronize()
             e0.record()
