@@ -63,15 +63,17 @@ __global__ __launch_bounds__(NT, OCC) void k_path_chunk(TraceParams P, int k0, i
   __shared__ typename PathEngine<VT, NT, RPT, MAXM, MF, VL>::Smem S;
   __shared__ double red[NT / 64];
   __shared__ PathCarry carry;
+  __shared__ PathTables tables;
   const int w = blockIdx.x;
   if (w >= P.counters[0]) return;
+  path_tables_load<NT>(P, tables);
   {
     // stop at this path's own length (uniform over the workgroup)
     const int c = P.work[w] / P.n_ret;
     const int64_t n = cfg_end(P, c) - P.offsets[c];
     if (int64_t(k1) > n) k1 = int(n);
   }
-  path_run<VT, NT, RPT, MAXM, MF, VL>(P, w, k0, k1, S, red, carry);
+  path_run<VT, NT, RPT, MAXM, MF, VL>(P, w, k0, k1, S, red, carry, tables);
 }
 
 template <typename VT, int NT, int RPT>
@@ -92,14 +94,16 @@ __global__ void k_reduce(TraceParams P, double* out_log, int8_t* out_sign, int32
     reduce_config(P, c, out_log, out_sign, out_steps, out_sub, out_feas, out_rowsteps, out_rows);
 }
 
-// Operator application on a batch of vectors (parity hook): the trace kernels'
-// own gather (gather_op), one thread per output component.
-__global__ void k_apply_op(const uint32_t* states, const int32_t* rank, BlockDev Bin, BlockDev Bout, int f,
-                           int dagger, int n_vec, const double* x, double* y) {
+// Operator application on a batch of vectors (parity hook): the whole-path trace
+// kernel's own gather (gather_tab on the LDS tables), one thread per output component.
+__global__ __launch_bounds__(256) void k_apply_op(TraceParams P, BlockDev Bin, BlockDev Bout, int f, int dagger,
+                                                  int n_vec, const double* x, double* y) {
+  __shared__ PathTables tables;
+  path_tables_load<256>(P, tables);
   const int64_t id = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (id >= int64_t(n_vec) * Bout.dim) return;
   const int v = int(id / Bout.dim), r = int(id - int64_t(v) * Bout.dim);
-  y[id] = gather_op<double>(states, rank, Bout, r, f, dagger, x + int64_t(v) * Bin.dim);
+  y[id] = gather_tab<double>(tables, P.n_orb, Bin, Bout, r, f, dagger, x + int64_t(v) * Bin.dim);
 }
 
 // Krylov propagation of a batch of vectors of one block (parity hook): one
@@ -958,8 +962,8 @@ int hyb_apply_op_device(hyb_model* m, int32_t f, int32_t dagger, int32_t bin, in
   const int64_t total = int64_t(n_vec) * m->blocks[bt].dim;
   if (total == 0) return HYB_OK;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  k_apply_op<<<unsigned((total + 255) / 256), 256, 0, s>>>(m->dev.states, m->dev.rank, B, m->blocks[bt], f, dagger,
-                                                           n_vec, x, y);
+  const TraceParams P = base_params(m);
+  k_apply_op<<<unsigned((total + 255) / 256), 256, 0, s>>>(P, B, m->blocks[bt], f, dagger, n_vec, x, y);
   HIP_TRY(hipGetLastError());
   return HYB_OK;
 }

@@ -3,11 +3,12 @@
 // One workgroup carries one feasible (configuration, retained state) path through
 // all of its operators in one launch (k_path_chunk with the whole operator range;
 // shorter chunks, down to one operator per launch, give the same arithmetic in
-// another launch schedule).  Between operators a path's state (block, log-scale,
-// unit vector) passes through global memory.  Inside a propagation the vector
-// lives in registers, RPT rows per thread (row = tid + k*NT), the Lanczos basis
-// V_0..V_m lives in registers too, and LDS holds the vector being gathered by the
-// SpMV, the block's off-diagonal rows, the reduction partials and the small
+// another launch schedule).  Inside a launch a path's state (block, log-scale,
+// unit vector) stays on chip (path_run); it passes through global memory only
+// between launches.  The vector lives in registers, RPT rows per thread (row =
+// tid + k*NT), the Lanczos basis V_0..V_m lives in registers too, and LDS holds the
+// vector being gathered by the SpMV or the operator, the block's off-diagonal rows,
+// the model's block and spin-pattern tables, the reduction partials and the small
 // tridiagonal problem.
 //
 // Steps (Sec. III): the retained eigenstate enters with the scalar phase of the
@@ -1484,20 +1485,70 @@ struct PathCarry {
   int32_t steps, subs;
 };
 
+// The model's block table and the one-spin pattern tables (n_orb <= 7), copied into
+// LDS once per launch, so that an operator's target block, the target states and the
+// source ranks come from LDS and integer arithmetic instead of dependent global
+// loads.  Pattern i (ascending) with c bits set is pat[off[c] + i]; rank_half inverts
+// it; the state of row r of block (n_up, n_dn) is pat[off[n_up] + r % up_states] |
+// pat[off[n_dn] + r / up_states] << n_orb.
+struct PathTables {
+  BlockDev blk[64];
+  int16_t rh[128];
+  uint8_t pat[128];
+  int16_t off[8];
+};
+
+template <int NT>
+__device__ inline void path_tables_load(const TraceParams& P, PathTables& T) {
+  const int n = P.n_orb, nb = (n + 1) * (n + 1), ns = 1 << n;
+  for (int i = threadIdx.x; i < nb; i += NT) T.blk[i] = P.blocks[i];
+  for (int i = threadIdx.x; i < ns; i += NT) T.rh[i] = P.rank_half[i];
+  if (int(threadIdx.x) <= n) {
+    // patterns with fewer than c bits: sum of C(n, c') over c' < c
+    const int c = threadIdx.x;
+    int off = 0, b = 1;
+    for (int q = 0; q < c; ++q) {
+      off += b;
+      b = b * (n - q) / (q + 1);
+    }
+    T.off[c] = int16_t(off);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < ns; i += NT) T.pat[T.off[__popc(i)] + T.rh[i]] = uint8_t(i);
+  __syncthreads();
+}
+
+// gather_op with the states and ranks from the LDS tables: component r of O x in the
+// target block Bt for x in the source block B (the same moves and sign flips).
+template <typename VT>
+__device__ __forceinline__ VT gather_tab(const PathTables& T, int n, const BlockDev& B, const BlockDev& Bt, int r,
+                                         int f, int dg, const VT* x) {
+  const uint32_t bit = 1u << f, lo = (1u << n) - 1u;
+  const int dr = r / Bt.up_states, ur = r - dr * Bt.up_states;
+  const uint32_t t = uint32_t(T.pat[T.off[Bt.n_up] + ur]) | (uint32_t(T.pat[T.off[Bt.n_dn] + dr]) << n);
+  const bool has = dg ? ((t & bit) != 0u) : ((t & bit) == 0u);
+  if (!has) return VT(0);
+  const uint32_t s = t ^ bit;
+  const VT v = x[int(T.rh[s >> n]) * B.up_states + int(T.rh[s & lo])];
+  return (__popc(s & (bit - 1u)) & 1) ? -v : v;
+}
+
 // Steps 4-5 for operators [k0, k1) of one path, fused: the same arithmetic as
 // path_prop / path_op in the same order, with the vector in registers, the totals
-// in LDS and the operator's gather reading the vector from LDS, so that only the
-// first and the last operator touch the path's global state.  k1 must not exceed
-// the configuration's operator count.
+// in LDS and the operator's gather reading the vector and the model tables from LDS,
+// so that only the first and the last operator touch the path's global state.  The
+// next operator's flavor, type and time are requested before each propagation.  k1
+// must not exceed the configuration's operator count.
 template <typename VT, int NT, int RPT, int MAXM, bool MF, bool VL>
 __device__ inline void path_run(const TraceParams& P, int w, int k0, int k1,
                                 typename PathEngine<VT, NT, RPT, MAXM, MF, VL>::Smem& S, double* red,
-                                PathCarry& pc) {
+                                PathCarry& pc, const PathTables& T) {
   using E = PathEngine<VT, NT, RPT, MAXM, MF, VL>;
   if (k0 >= k1 || P.st_status[w] != PATH_ACTIVE) return;
   const int id = P.work[w];
   const int c = id / P.n_ret;
   const int64_t o0 = P.offsets[c];
+  const int n = P.n_orb;
   E eng(P, S);
   int status = PATH_ACTIVE;
   int blk = P.st_block[w];
@@ -1510,7 +1561,7 @@ __device__ inline void path_run(const TraceParams& P, int w, int k0, int k1,
   }
   VT x[RPT];
   {
-    const int dim = P.blocks[blk].dim;
+    const int dim = T.blk[blk].dim;
     const VT* vec = path_vec<VT>(P, k0 & 1, w);
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
@@ -1520,15 +1571,21 @@ __device__ inline void path_run(const TraceParams& P, int w, int k0, int k1,
   }
   // the vector in LDS for the operator's gather (VL engines keep no separate copy)
   VT* xs = VL ? S.vb : S.vec;
+  double tprev = (k0 > 0) ? P.tau[o0 + k0 - 1] : 0.0;
+  double tcur = P.tau[o0 + k0];
   int k = k0;
   for (; k < k1; ++k) {
+    // operator k's data, and the next time, requested before the propagation
+    const int f = P.flavor[o0 + k];
+    const int dg = P.dagger[o0 + k] ? 1 : 0;
+    const double tnext = (k + 1 < k1) ? P.tau[o0 + k + 1] : 0.0;
+    const BlockDev B = T.blk[blk];
     if (k > 0) {
-      const BlockDev B = P.blocks[blk];
       double ell = 0.0;
       int steps = 0, subs = 0;
       eng.work = 0;
       eng.nops_budget = 1;
-      const bool ok = eng.propagate(B, P.tau[o0 + k] - P.tau[o0 + k - 1], x, ell, steps, subs);
+      const bool ok = eng.propagate(B, tcur - tprev, x, ell, steps, subs);
       if (threadIdx.x == 0) {
         pc.ell += ell;
         pc.steps += steps;
@@ -1541,18 +1598,17 @@ __device__ inline void path_run(const TraceParams& P, int w, int k0, int k1,
         break;
       }
     }
+    tprev = tcur;
+    tcur = tnext;
     // operator k: signed gather from the source block into the target block
-    const int f = P.flavor[o0 + k];
-    const int dg = P.dagger[o0 + k] ? 1 : 0;
-    const BlockDev B = P.blocks[blk];
     int nu = B.n_up, nd = B.n_dn;
-    if (f < P.n_orb) nu += dg ? 1 : -1; else nd += dg ? 1 : -1;
-    if (nu < 0 || nu > P.n_orb || nd < 0 || nd > P.n_orb) {  // excluded by the scan
+    if (f < n) nu += dg ? 1 : -1; else nd += dg ? 1 : -1;
+    if (nu < 0 || nu > n || nd < 0 || nd > n) {  // excluded by the scan
       status = PATH_FAILED;
       break;
     }
-    const int bt = nd * (P.n_orb + 1) + nu;
-    const BlockDev Bt = P.blocks[bt];
+    const int bt = nd * (n + 1) + nu;
+    const BlockDev Bt = T.blk[bt];
     __syncthreads();  // the propagation's last LDS reads are done
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
@@ -1565,7 +1621,7 @@ __device__ inline void path_run(const TraceParams& P, int w, int k0, int k1,
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
       const int r = eng.row(q);
-      const VT v = (r < Bt.dim) ? gather_op<VT>(P.states, P.rank, Bt, r, f, dg, xs) : VT(0);
+      const VT v = (r < Bt.dim) ? gather_tab<VT>(T, n, B, Bt, r, f, dg, xs) : VT(0);
       val[q] = v;
       part += to_d(v) * to_d(v);
     }
@@ -1594,7 +1650,7 @@ __device__ inline void path_run(const TraceParams& P, int w, int k0, int k1,
   }
   if (status == PATH_ACTIVE) {
     // operators [k0, k1) applied: the vector goes where operator k1 - 1 leaves it
-    const int dim = P.blocks[blk].dim;
+    const int dim = T.blk[blk].dim;
     VT* vec = path_vec<VT>(P, k1 & 1, w);
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
