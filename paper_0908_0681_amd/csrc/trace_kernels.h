@@ -1536,8 +1536,7 @@ __device__ __forceinline__ VT gather_tab(const PathTables& T, int n, const Block
 // Steps 4-5 for operators [k0, k1) of one path, fused: the same arithmetic as
 // path_prop / path_op in the same order, with the vector in registers, the totals
 // in LDS and the operator's gather reading the vector and the model tables from LDS,
-// so that only the first and the last operator touch the path's global state.  The
-// next operator's flavor, type and time are requested before each propagation.  k1
+// so that only the first and the last operator touch the path's global state.  k1
 // must not exceed the configuration's operator count.
 template <typename VT, int NT, int RPT, int MAXM, bool MF, bool VL>
 __device__ inline void path_run(const TraceParams& P, int w, int k0, int k1,
@@ -1571,21 +1570,15 @@ __device__ inline void path_run(const TraceParams& P, int w, int k0, int k1,
   }
   // the vector in LDS for the operator's gather (VL engines keep no separate copy)
   VT* xs = VL ? S.vb : S.vec;
-  double tprev = (k0 > 0) ? P.tau[o0 + k0 - 1] : 0.0;
-  double tcur = P.tau[o0 + k0];
   int k = k0;
   for (; k < k1; ++k) {
-    // operator k's data, and the next time, requested before the propagation
-    const int f = P.flavor[o0 + k];
-    const int dg = P.dagger[o0 + k] ? 1 : 0;
-    const double tnext = (k + 1 < k1) ? P.tau[o0 + k + 1] : 0.0;
     const BlockDev B = T.blk[blk];
     if (k > 0) {
       double ell = 0.0;
       int steps = 0, subs = 0;
       eng.work = 0;
       eng.nops_budget = 1;
-      const bool ok = eng.propagate(B, tcur - tprev, x, ell, steps, subs);
+      const bool ok = eng.propagate(B, P.tau[o0 + k] - P.tau[o0 + k - 1], x, ell, steps, subs);
       if (threadIdx.x == 0) {
         pc.ell += ell;
         pc.steps += steps;
@@ -1598,9 +1591,9 @@ __device__ inline void path_run(const TraceParams& P, int w, int k0, int k1,
         break;
       }
     }
-    tprev = tcur;
-    tcur = tnext;
     // operator k: signed gather from the source block into the target block
+    const int f = P.flavor[o0 + k];
+    const int dg = P.dagger[o0 + k] ? 1 : 0;
     int nu = B.n_up, nd = B.n_dn;
     if (f < n) nu += dg ? 1 : -1; else nd += dg ? 1 : -1;
     if (nu < 0 || nu > n || nd < 0 || nd > n) {  // excluded by the scan
