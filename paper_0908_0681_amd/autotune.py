@@ -39,8 +39,8 @@ def gpu_arch() -> str:
 
 
 def tune(w, reps: int = 3, n_configs: int | None = None) -> dict:
-    """Times every fitting variant, then the launch schedules of the fastest, on
-    workload w (an inputs.Workload)."""
+    """Times every fitting variant with the whole path in one launch, then the launch
+    schedules of the fastest, on workload w (an inputs.Workload)."""
     import torch
     from . import hyb
     model = hyb.model_for_workload(w, use_cache=False)
@@ -49,6 +49,7 @@ def tune(w, reps: int = 3, n_configs: int | None = None) -> dict:
     out = {"log_abs": torch.empty(batch.n_configs, dtype=torch.float64, device="cuda"),
            "sign": torch.empty(batch.n_configs, dtype=torch.int8, device="cuda")}
     results = {}
+    model.set_chunk(0)  # variants are ranked under the schedule they will run with
     for v, name in enumerate(hyb.variant_names()):
         try:
             model.set_variant(v)
