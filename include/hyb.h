@@ -178,8 +178,9 @@ int hyb_apply_op(const hyb_model* m, int32_t flavor, int32_t dagger, int32_t blo
 /* ---- device parity hooks --------------------------------------------------- */
 
 /* Device operator application to n_vec vectors of block block_in, through the
- * same gather function (gather_op) that the trace kernels apply at every operator
- * of a path (Sec. III step 4).  x: device [n_vec][dim_in], y: device
+ * same gather function (gather_tab: target states and source ranks from the
+ * model's block and spin-pattern tables in LDS) that the whole-path trace kernel
+ * applies at every operator of a path (Sec. III step 4).  x: device [n_vec][dim_in], y: device
  * [n_vec][dim_out].  Bit-exact: only sign flips and moves.  *block_out = -1 (and y
  * untouched) when the operator leaves the physical range. */
 int hyb_apply_op_device(hyb_model* m, int32_t flavor, int32_t dagger, int32_t block_in,
