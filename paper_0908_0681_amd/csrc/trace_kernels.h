@@ -196,8 +196,8 @@ __device__ __forceinline__ double rcp_d(double d) {
 // without cancellation.
 __device__ __forceinline__ double pole_root(double w, double s, bool right) {
   const double sq = sqrt(w * w + 4.0 * s);
-  if (right) return (w < 0.0) ? 2.0 * s / (sq - w) : 0.5 * (w + sq);
-  return (w > 0.0) ? -2.0 * s / (w + sq) : 0.5 * (w - sq);
+  if (right) return (w < 0.0) ? 2.0 * s * rcp_d(sq - w) : 0.5 * (w + sq);
+  return (w > 0.0) ? -2.0 * s * rcp_d(w + sq) : 0.5 * (w - sq);
 }
 
 // True on every lane when p holds on at least one lane of the wavefront.
@@ -1192,7 +1192,7 @@ struct PathEngine {
           const double yn2 = wave_sum(wl * wl);
           const double ylast = wave_sum(qj * wl);
           ynorm = sqrt(yn2);
-          const double est = bj * fabs(ylast) / ynorm;
+          const double est = bj * fabs(ylast) * rcp_d(ynorm);
           ok = (est <= P.tol) || (bj <= breakdown);
           if (ok || !last) break;
           tau_try *= 0.5;  // depth cap reached: shorten the substep
@@ -1221,7 +1221,7 @@ struct PathEngine {
           atomicOr(&P.counters[2], ERR_NOCONV);
           return false;
         }
-        const double inv = 1.0 / bj;
+        const double inv = rcp_d(bj);
 #pragma unroll
         for (int i = 1; i <= MAXM; ++i)
           if (i == j + 1) {
@@ -1230,7 +1230,7 @@ struct PathEngine {
           }
       }
       // recombination x = V_m y / ||y||
-      const double inv = 1.0 / ynorm;
+      const double inv = rcp_d(ynorm);
 #pragma unroll
       for (int k = 0; k < RPT; ++k) {
         double t = 0.0;
@@ -1426,7 +1426,7 @@ __device__ inline void path_op(const TraceParams& P, int w, int k, double* red) 
     }
     return;
   }
-  const double inv = 1.0 / sqrt(n2);
+  const double inv = rcp_d(sqrt(n2));
 #pragma unroll
   for (int q = 0; q < RPT; ++q) {
     const int r = threadIdx.x + q * NT;
@@ -1632,7 +1632,7 @@ __device__ inline void path_run(const TraceParams& P, int w, int k0, int k1,
       if (!zero && threadIdx.x == 0) atomicOr(&P.counters[2], ERR_NONFINITE);
       break;
     }
-    const double inv = 1.0 / sqrt(n2);
+    const double inv = rcp_d(sqrt(n2));
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
       const int r = eng.row(q);
