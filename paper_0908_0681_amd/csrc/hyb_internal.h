@@ -18,7 +18,8 @@ struct BlockDev {
   int32_t n_up, n_dn;
   double shift;       // c_b: lowest eigenvalue of the block; kernels apply H_b - c_b
   int32_t up_states;  // C(n_orb, n_up): index of state (up, dn) = rank_half[dn] * up_states + rank_half[up]
-  int32_t pad_;
+  float width;        // spectral width of the block (exact with the host spectrum, else a
+                      // Gershgorin bound): weights a path's expected cost in the queue order
 };
 
 struct DeviceModel {

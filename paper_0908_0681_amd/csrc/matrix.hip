@@ -81,8 +81,12 @@ __global__ void k_mat_init(int32_t* c) {
 }
 
 __global__ void k_mat_scan(TraceParams P) {
+  __shared__ float width[64];  // (n_orb + 1)^2 <= 64 blocks
+  const int nb = (P.n_orb + 1) * (P.n_orb + 1);
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) width[i] = P.blocks[i].width;
+  __syncthreads();
   const int64_t id = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (id < int64_t(P.n_configs) * P.n_ret) scan_pair(P, id);
+  if (id < int64_t(P.n_configs) * P.n_ret) scan_pair(P, id, width);
 }
 
 __global__ void k_mat_reduce(TraceParams P, double* out_log, int8_t* out_sign, int32_t* out_steps, int32_t* out_sub,

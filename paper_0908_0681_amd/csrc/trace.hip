@@ -26,13 +26,34 @@ namespace hyb {
 // kernels
 // ---------------------------------------------------------------------------
 
-__global__ void k_init_counters(int32_t* c) {
-  if (threadIdx.x < 4) c[threadIdx.x] = 0;
+__global__ void k_init_counters(int32_t* c, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) c[i] = 0;
 }
 
 __global__ void k_scan(TraceParams P) {
+  __shared__ float width[64];  // (n_orb + 1)^2 <= 64 blocks
+  const int nb = (P.n_orb + 1) * (P.n_orb + 1);
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) width[i] = P.blocks[i].width;
+  __syncthreads();
   const int64_t id = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (id < int64_t(P.n_configs) * P.n_ret) scan_pair(P, id);
+  if (id < int64_t(P.n_configs) * P.n_ret) scan_pair(P, id, width);
+}
+
+// First queue slot of every cost bucket, the costliest bucket first (one workgroup
+// of ORDER_NB threads).
+__global__ void k_order_base(int32_t* c) {
+  const int b = threadIdx.x;
+  int s = 0;
+  for (int q = b + 1; q < ORDER_NB; ++q) s += c[4 + q];
+  c[4 + ORDER_NB + b] = s;
+}
+
+// Every feasible path into the next slot of its bucket.
+__global__ void k_order_place(TraceParams P) {
+  const int64_t id = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (id >= int64_t(P.n_configs) * P.n_ret) return;
+  const int b = P.p_bucket[id];
+  if (b >= 0) P.work[atomicAdd(&P.counters[4 + ORDER_NB + b], 1)] = int32_t(id);
 }
 
 template <typename VT, int NT>
@@ -318,7 +339,7 @@ static int error_from_bits(int bits) {
 
 namespace {
 struct ResidentLayout {
-  size_t cnt, work, psign, plog, psteps, psub, prs, prw, srs, srw, sblock, sstatus, ssteps, ssubs, sell, midblk, svec,
+  size_t cnt, work, pbucket, psign, plog, psteps, psub, prs, prw, srs, srw, sblock, sstatus, ssteps, ssubs, sell, midblk, svec,
       total;
 };
 ResidentLayout resident_layout(const hyb_model* m, int nc, size_t vbytes) {
@@ -331,8 +352,9 @@ ResidentLayout resident_layout(const hyb_model* m, int nc, size_t vbytes) {
     off = align_up(off + bytes);
     return o;
   };
-  L.cnt = take(4 * sizeof(int32_t));
+  L.cnt = take(COUNTERS_LEN * sizeof(int32_t));
   L.work = take(npairs * sizeof(int32_t));
+  L.pbucket = take(npairs * sizeof(int32_t));
   L.psign = take(npairs * sizeof(int8_t));
   L.plog = take(npairs * sizeof(double));
   L.psteps = take(npairs * sizeof(int32_t));
@@ -366,6 +388,7 @@ static TraceParams resident_params(const hyb_model* m, int nc, void* ws, size_t 
   P.n_pairs = int32_t(int64_t(nc) * int64_t(m->ret_block.size()));
   P.counters = reinterpret_cast<int32_t*>(w + L.cnt);
   P.work = reinterpret_cast<int32_t*>(w + L.work);
+  P.p_bucket = reinterpret_cast<int32_t*>(w + L.pbucket);
   P.p_sign = reinterpret_cast<int8_t*>(w + L.psign);
   P.p_log = reinterpret_cast<double*>(w + L.plog);
   P.p_steps = reinterpret_cast<int32_t*>(w + L.psteps);
@@ -393,10 +416,12 @@ static int resident_launch(const Variant& V, TraceParams& P, int max_ops, double
                            int32_t* out_steps, int32_t* out_sub, int32_t* out_feas, int64_t* out_rs, int64_t* out_rw,
                            hipStream_t s) {
   const int64_t npairs = P.n_pairs;
-  k_init_counters<<<1, 64, 0, s>>>(P.counters);
+  k_init_counters<<<1, 256, 0, s>>>(P.counters, COUNTERS_LEN);
   const int scan_threads = 256;
   k_scan<<<unsigned((npairs + scan_threads - 1) / scan_threads), scan_threads, 0, s>>>(P);
   if (npairs > 0) {
+    k_order_base<<<1, ORDER_NB, 0, s>>>(P.counters);
+    k_order_place<<<unsigned((npairs + 255) / 256), 256, 0, s>>>(P);
     int k0 = 0, k1 = max_ops;
     void* a0[] = {&P};
     void* ak[] = {&P, &k0, &k1};
@@ -568,6 +593,26 @@ int hyb_model_upload(hyb_model* m, void* stream) {
   if ((rc = dev_upload(d.states, m->states.data(), m->states.size(), s))) return rc;
   if ((rc = dev_upload(d.rank, m->rank.data(), m->rank.size(), s))) return rc;
   if ((rc = dev_upload(d.rank_half, m->rank_half.data(), m->rank_half.size(), s))) return rc;
+  // spectral width of every block (exact from the host spectrum, else a Gershgorin
+  // bound): the scan's cost estimate for ordering the path queue
+  for (int b = 0; b < m->n_blocks; ++b) {
+    BlockDev& B = m->blocks[b];
+    double w = 0.0;
+    if (!m->evals.empty() && !m->evals[b].empty()) {
+      w = m->evals[b].back() - m->evals[b].front();
+    } else if (B.dim > 0) {
+      double lo = INFINITY, hi = -INFINITY;
+      for (int i = 0; i < B.dim; ++i) {
+        const int64_t g = B.state_off + i;
+        double r = 0.0;
+        for (int j = m->rowptr[g]; j < m->rowptr[g + 1]; ++j) r += std::fabs(m->val[j]);
+        lo = std::min(lo, m->diag[g] - r);
+        hi = std::max(hi, m->diag[g] + r);
+      }
+      w = hi - lo;
+    }
+    B.width = float(w);
+  }
   if ((rc = dev_upload(d.blocks, m->blocks.data(), m->blocks.size(), s))) return rc;
   // the off-diagonal matrix (CSR and both ELL copies) only for CSR storage; a
   // matrix-free model keeps one-element placeholders
@@ -702,8 +747,9 @@ int hyb_trace_batch(hyb_model* m, const hyb_config_batch* cfg, double beta, hyb_
     off = align_up(off + bytes);
     return o;
   };
-  const size_t o_cnt = take(4 * sizeof(int32_t));
+  const size_t o_cnt = take(COUNTERS_LEN * sizeof(int32_t));
   const size_t o_work = take(npairs * sizeof(int32_t));
+  const size_t o_pbucket = take(npairs * sizeof(int32_t));
   const size_t o_psign = take(npairs * sizeof(int8_t));
   const size_t o_plog = take(npairs * sizeof(double));
   const size_t o_psteps = take(npairs * sizeof(int32_t));
@@ -747,6 +793,7 @@ int hyb_trace_batch(hyb_model* m, const hyb_config_batch* cfg, double beta, hyb_
   P.beta = beta;
   P.counters = reinterpret_cast<int32_t*>(ws + o_cnt);
   P.work = reinterpret_cast<int32_t*>(ws + o_work);
+  P.p_bucket = reinterpret_cast<int32_t*>(ws + o_pbucket);
   P.p_sign = reinterpret_cast<int8_t*>(ws + o_psign);
   P.p_log = reinterpret_cast<double*>(ws + o_plog);
   P.p_steps = reinterpret_cast<int32_t*>(ws + o_psteps);
@@ -793,10 +840,14 @@ int hyb_trace_batch(hyb_model* m, const hyb_config_batch* cfg, double beta, hyb_
 
   hipEvent_t ev[4];
   for (int i = 0; i < 4; ++i) ev[i] = reinterpret_cast<hipEvent_t>(m->events[i]);
-  k_init_counters<<<1, 64, 0, s>>>(P.counters);
+  k_init_counters<<<1, 256, 0, s>>>(P.counters, COUNTERS_LEN);
   if (m->timing) HIP_TRY(hipEventRecord(ev[0], s));
   const int scan_threads = 256;
   k_scan<<<unsigned((npairs + scan_threads - 1) / scan_threads), scan_threads, 0, s>>>(P);
+  if (npairs > 0) {
+    k_order_base<<<1, ORDER_NB, 0, s>>>(P.counters);
+    k_order_place<<<unsigned((npairs + 255) / 256), 256, 0, s>>>(P);
+  }
   HIP_TRY(hipGetLastError());
   // queued paths, longest configuration and validation errors
   int32_t cnt[3] = {0, 0, 0};
@@ -982,7 +1033,7 @@ int hyb_propagate_device(hyb_model* m, int32_t block, int32_t n_vec, const void*
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   TraceParams P = base_params(m);
   P.counters = static_cast<int32_t*>(m->dev.ws);
-  k_init_counters<<<1, 64, 0, s>>>(P.counters);
+  k_init_counters<<<1, 64, 0, s>>>(P.counters, 4);
   void* args[] = {&P, &block, (void*)&x, (void*)&dtau, &y, &log_scale, &steps};
   HIP_TRY(hipLaunchKernel(V.prop_fn, dim3(unsigned(n_vec)), dim3(V.nt), args, 0, s));
   int32_t flags = 0;

@@ -28,6 +28,12 @@ namespace hyb {
 
 enum : int32_t { ERR_UNSORTED = 1, ERR_FLAVOR = 2, ERR_NOCONV = 4, ERR_NONFINITE = 8, ERR_SINGULAR = 16 };
 
+// The path queue is ordered by an estimate of each path's cost, longest first, so
+// that the launch does not end with long paths started late: Sum over the path's
+// intervals of sqrt(dtau * width of the block), in ORDER_NB logarithmic buckets.
+constexpr int ORDER_NB = 128;
+constexpr int COUNTERS_LEN = 4 + 2 * ORDER_NB;
+
 struct TraceParams {
   // model
   const uint32_t* states;
@@ -55,7 +61,10 @@ struct TraceParams {
   double beta;
   // work queue and per-path results (path id = config * n_ret + r)
   int32_t* work;
-  int32_t* counters;  // [0] queued paths, [1] longest configuration, [2] error bits
+  int32_t* counters;  // [0] queued paths, [1] longest configuration, [2] error bits;
+                      // [4, 4 + ORDER_NB) paths per cost bucket, then each bucket's next slot
+  int32_t* p_bucket;  // per pair: cost bucket of a feasible path, -1 otherwise (nullptr:
+                      // the scan queues paths in the order it finds them)
   int8_t* p_sign;
   double* p_log;
   int32_t* p_steps;
@@ -1248,7 +1257,7 @@ struct PathEngine {
 
 };
 
-__device__ inline void scan_pair(const TraceParams& P, int64_t id) {
+__device__ inline void scan_pair(const TraceParams& P, int64_t id, const float* width) {
   const int c = int(id / P.n_ret), r = int(id - int64_t(c) * P.n_ret);
   const int64_t o0 = P.offsets[c], o1 = cfg_end(P, c);
   int err = 0;
@@ -1256,11 +1265,13 @@ __device__ inline void scan_pair(const TraceParams& P, int64_t id) {
   int nu = B0.n_up, nd = B0.n_dn;
   int mid = P.ret_block[r];
   bool feas = true;
-  double prev = -1.0;
+  double prev = -1.0, cost = 0.0;
   if (o1 < o0) err |= ERR_UNSORTED;
   for (int64_t k = o0; k < o1; ++k) {
     const double t = P.tau[k];
     if (!(t >= 0.0) || !(t < P.beta) || !(t > prev)) err |= ERR_UNSORTED;
+    // the interval before operator k, spent in the block the path is in
+    if (k > o0 && feas) cost += sqrt(fmax(t - prev, 0.0) * double(width[nd * (P.n_orb + 1) + nu]));
     prev = t;
     const int f = P.flavor[k];
     const int dg = P.dagger[k];
@@ -1284,7 +1295,15 @@ __device__ inline void scan_pair(const TraceParams& P, int64_t id) {
   P.p_rows[id] = 0;
   if (err && r == 0) atomicOr(&P.counters[2], err);
   if (r == 0 && o1 > o0) atomicMax(&P.counters[1], int(o1 - o0));
-  if (feas) {
+  if (P.p_bucket) {
+    int b = -1;
+    if (feas) {
+      b = min(ORDER_NB - 1, int(8.0 * log2(1.0 + cost)));
+      atomicAdd(&P.counters[0], 1);
+      atomicAdd(&P.counters[4 + b], 1);
+    }
+    P.p_bucket[id] = b;
+  } else if (feas) {
     const int slot = atomicAdd(&P.counters[0], 1);
     P.work[slot] = int32_t(id);
   }
