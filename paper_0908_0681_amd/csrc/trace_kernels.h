@@ -29,8 +29,8 @@ namespace hyb {
 enum : int32_t { ERR_UNSORTED = 1, ERR_FLAVOR = 2, ERR_NOCONV = 4, ERR_NONFINITE = 8, ERR_SINGULAR = 16 };
 
 // The path queue is ordered by an estimate of each path's cost, longest first, so
-// that the launch does not end with long paths started late: Sum over the path's
-// intervals of sqrt(dtau * width of the block), in ORDER_NB logarithmic buckets.
+// that the launch does not end with long paths started late: the sum over the path's
+// intervals of (dtau * width of the block)^(3/4), in ORDER_NB logarithmic buckets.
 constexpr int ORDER_NB = 128;
 constexpr int COUNTERS_LEN = 4 + 2 * ORDER_NB;
 
@@ -1271,7 +1271,10 @@ __device__ inline void scan_pair(const TraceParams& P, int64_t id, const float* 
     const double t = P.tau[k];
     if (!(t >= 0.0) || !(t < P.beta) || !(t > prev)) err |= ERR_UNSORTED;
     // the interval before operator k, spent in the block the path is in
-    if (k > o0 && feas) cost += sqrt(fmax(t - prev, 0.0) * double(width[nd * (P.n_orb + 1) + nu]));
+    if (k > o0 && feas) {
+      const double sq = sqrt(fmax(t - prev, 0.0) * double(width[nd * (P.n_orb + 1) + nu]));
+      cost += sq * sqrt(sq);
+    }
     prev = t;
     const int f = P.flavor[k];
     const int dg = P.dagger[k];
