@@ -28,7 +28,7 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch of the path kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE,
 # scaled by the same counters on a plain 1 GiB device copy (FETCH_SIZE x2.0,
 # WRITE_SIZE x1.0); None once the kernel changes after the counters were taken.
-TRAFFIC = {"kanamori-5orb-b50": 27_979_992.0, "kanamori-7orb-b40": 25_408_672.0}
+TRAFFIC = {"kanamori-5orb-b50": 27_966_988.0, "kanamori-7orb-b40": 25_353_267.2}
 
 
 def device_batch(batch, torch):

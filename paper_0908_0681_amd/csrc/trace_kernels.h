@@ -1100,7 +1100,9 @@ struct PathEngine {
           spmv(B, vj, w, dg, staged);
         }
         // classical Gram-Schmidt twice against V_0..V_j; the second round also
-        // reduces ||w||^2 so that beta_j needs no extra round
+        // reduces ||w||^2 so that beta_j needs no extra round.  A lane's products
+        // and updates run in the vector precision VT (FP32 for mixed paths, whose
+        // basis is stored in FP32 anyway), the sums across lanes and ||w||^2 in FP64.
         double hj;
         {
           double h[NRED];
@@ -1109,17 +1111,19 @@ struct PathEngine {
 #pragma unroll
           for (int i = 0; i < MAXM; ++i)
             if (i <= j) {
+              VT hp = VT(0);
 #pragma unroll
-              for (int k = 0; k < RPT; ++k) h[i] += to_d(VA(i, k)) * to_d(w[k]);
+              for (int k = 0; k < RPT; ++k) hp += VA(i, k) * w[k];
+              h[i] = to_d(hp);
             }
           block_sum<NRED>(h, j + 1);
 #pragma unroll
           for (int k = 0; k < RPT; ++k) {
-            double t = to_d(w[k]);
+            VT t = w[k];
 #pragma unroll
             for (int i = 0; i < MAXM; ++i)
-              if (i <= j) t -= h[i] * to_d(VA(i, k));
-            w[k] = static_cast<VT>(t);
+              if (i <= j) t -= static_cast<VT>(h[i]) * VA(i, k);
+            w[k] = t;
           }
           hj = h[0];
 #pragma unroll
@@ -1132,14 +1136,20 @@ struct PathEngine {
 #pragma unroll
           for (int i = 0; i < NRED; ++i) h[i] = 0.0;
           double wn = 0.0;
+          VT hp[MAXM];
+#pragma unroll
+          for (int i = 0; i < MAXM; ++i) hp[i] = VT(0);
 #pragma unroll
           for (int k = 0; k < RPT; ++k) {
             const double wd = to_d(w[k]);
 #pragma unroll
             for (int i = 0; i < MAXM; ++i)
-              if (i <= j) h[i] += to_d(VA(i, k)) * wd;
+              if (i <= j) hp[i] += VA(i, k) * w[k];
             wn += wd * wd;
           }
+#pragma unroll
+          for (int i = 0; i < MAXM; ++i)
+            if (i <= j) h[i] = to_d(hp[i]);
 #pragma unroll
           for (int i = 1; i < NRED; ++i)
             if (i == j + 1) h[i] = wn;
@@ -1153,11 +1163,11 @@ struct PathEngine {
             if (i <= j) corr += h[i] * h[i];
 #pragma unroll
           for (int k = 0; k < RPT; ++k) {
-            double t = to_d(w[k]);
+            VT t = w[k];
 #pragma unroll
             for (int i = 0; i < MAXM; ++i)
-              if (i <= j) t -= h[i] * to_d(VA(i, k));
-            w[k] = static_cast<VT>(t);
+              if (i <= j) t -= static_cast<VT>(h[i]) * VA(i, k);
+            w[k] = t;
           }
           double h2j = h[0];
 #pragma unroll
